@@ -1,0 +1,237 @@
+/*
+ * litho.h -- C ABI of the MI355X (gfx950) SOCS aerial-image library.
+ *
+ * The calls follow the paper's statement of the imaging problem (Sec. III-A):
+ * a mask m, a normalised source S and a pupil P (NA cut-off plus a defocus
+ * aberration per focus plane F) go in; the partially coherent aerial image
+ * I(r; F) comes out.  The image is computed in the sum-of-coherent-systems
+ * form of Eqs. 3-4,
+ *
+ *     I(r) = D * sum_k lambda_k |E_k(r)|^2,   E_k = IDFT( Phi_k * DFT(m) ),
+ *
+ * where {lambda_k, Phi_k} are the leading eigenpairs of the TCC of Eq. 2.
+ * The resist is the sigmoid relaxation Z = 1 / (1 + exp(-a (I - t))) of the
+ * threshold model of Eqs. 5 and 17 (resist kernel = delta), and the ILT loss is
+ * L = sum_planes sum_r (Z - T)^2 against a target layout T.  The adjoint
+ * returns dL/dm for the pixel mask (the mask-gradient channel of Eq. 9).
+ *
+ * Conventions shared by every call:
+ *   - Return codes only (LITHO_OK or a negative LITHO_E_*); nothing throws or
+ *     aborts across the ABI.  litho_last_error() gives the reason as text
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Pointers named d_* are caller-owned DEVICE memory (HIP), pointers named
+ *     h_* are caller-owned HOST memory.  The library never frees them.
+ *   - Arrays are dense, row-major, float32 unless stated: a mask is
+ *     [batch][n][n], an image [batch][n_focus][n][n].
+ *   - Device calls are asynchronous on the caller's HIP stream (hipStream_t
+ *     passed as void*, NULL = the null stream).  Inputs must stay valid, and
+ *     outputs untouched, until that stream reaches the end of the call.
+ *   - A bank owns device memory (kernels, FFT tables, workspaces) until
+ *     litho_kernels_free().  Calls on different streams get separate
+ *     workspaces; calls on one stream are ordered by the stream.
+ *   - Grid sides n must be powers of two with 64 <= n <= 4096
+ *     (LITHO_E_UNSUPPORTED otherwise).
+ */
+#ifndef LITHO_H
+#define LITHO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LITHO_OK = 0,
+  LITHO_PENDING = 1,         /* serve: result not ready yet */
+  LITHO_E_INVALID = -1,      /* bad argument (NULL, size mismatch, out of range) */
+  LITHO_E_UNSUPPORTED = -2,  /* valid but not supported (grid side, precision) */
+  LITHO_E_NOMEM = -3,        /* device or host allocation failed / over budget */
+  LITHO_E_HIP = -4,          /* a HIP runtime call failed */
+  LITHO_E_BUSY = -5,         /* serve: queue full */
+  LITHO_E_NOTFOUND = -6      /* serve: unknown or already collected ticket */
+};
+
+/* Source shapes (Eq. 2's S), sampled on a G x G lattice over [-1, 1]^2 in units
+ * of NA with integer coordinates (i, j), sigma = (i, j) / ((G - 1) / 2).  A
+ * point is kept when sigma_in^2 h^2 <= i^2 + j^2 <= sigma_out^2 h^2 with
+ * h = (G - 1) / 2; the x-dipole also requires |j| <= |i|.  Kept points weigh
+ * the same and the weights sum to one. */
+enum { LITHO_SRC_ANNULAR = 0, LITHO_SRC_DIPOLE_X = 1 };
+
+/* Arithmetic of the per-kernel transforms.  FP32 is the plain form. */
+enum { LITHO_PREC_FP32 = 0 };
+
+/* Optical settings of one bank (Sec. III-A, Eqs. 1-2).  All lengths in nm.
+ * The clip of n x n pixels is one period of the transforms.  The pupil is
+ * P(f) = 1[|f| <= NA/lambda] exp(i 2 pi / lambda * F NA^2 / 4 * (2 rho^2 - 1)),
+ * rho = lambda |f| / NA (the defocus Zernike term, paraxial), one bank plane
+ * per focus value F in focus_nm. */
+typedef struct litho_optics {
+  int n;                    /* grid side in pixels */
+  double pixel_nm;          /* pixel size */
+  double wavelength_nm;     /* lambda */
+  double na;                /* numerical aperture */
+  int source_kind;          /* LITHO_SRC_* */
+  int source_grid;          /* G, odd, >= 3 */
+  double sigma_in;          /* inner radius, units of NA */
+  double sigma_out;         /* outer radius, units of NA, <= 1 */
+  int n_focus;              /* number of focus planes, 1..8 */
+  const double *focus_nm;   /* h_[n_focus] focus offsets F (copied) */
+  int K;                    /* SOCS kernels kept per plane (Eq. 3), 1..n_source */
+  double dose;              /* D of Eq. 1 (scales I); 0 is taken as 1 */
+} litho_optics_t;
+
+typedef struct litho_bank litho_bank_t;
+
+/* Geometry and spectrum of a bank. */
+typedef struct litho_bank_info {
+  int n;                    /* grid side */
+  int b;                    /* band half-width: |kx|, |ky| <= b, b = floor((1 + sigma_out) R) */
+  int B;                    /* band side 2b + 1 */
+  int K;                    /* kernels per plane */
+  int n_focus;              /* planes */
+  int n_source;             /* sampled source points (TCC rank bound) */
+  int inner_grid;           /* side of the grid the per-kernel transforms run on */
+  double pupil_radius;      /* R = NA n p / lambda in frequency-index units */
+  size_t device_bytes;      /* device memory held by the bank (without workspaces) */
+} litho_bank_info_t;
+
+/* Build the SOCS kernel bank of Eqs. 2-3 on the host in FP64 and upload it.
+ *   optics: read only during the call.  out: receives the new bank.
+ * The TCC = A A^H with A[f, s] = sqrt(S_s) P(f + sigma_s; F) is decomposed
+ * through the Hermitian source-space Gram matrix A^H A (own Jacobi solver),
+ * Phi_k = A nu_k / sqrt(lambda_k) with ||Phi_k||_2 = 1 over the band samples,
+ * eigenvalues in descending order.  Errors: LITHO_E_INVALID (bad optics),
+ * LITHO_E_UNSUPPORTED (n), LITHO_E_NOMEM / LITHO_E_HIP (upload). */
+int litho_kernels_build(const litho_optics_t *optics, litho_bank_t **out);
+
+/* Load a bank from caller-provided eigenpairs instead of building it.
+ *   h_lambda: [n_focus][K] eigenvalues (>= 0).
+ *   h_phi:    [n_focus][K][B][B][2] interleaved (re, im) float64, indexed
+ *             [ky + b][kx + b] (centred band order).
+ * Everything is copied.  The band side B must be odd and B <= n. */
+int litho_kernels_load(int n, int B, int K, int n_focus, const double *h_lambda,
+                       const double *h_phi, litho_bank_t **out);
+
+int litho_kernels_info(const litho_bank_t *bank, litho_bank_info_t *info);
+
+/* Copy the eigenvalues, h_lambda_out: [n_focus][K]. */
+int litho_kernels_eigenvalues(const litho_bank_t *bank, double *h_lambda_out);
+
+/* Copy kernel Phi_k of plane p (FP64, unit norm), h_phi_out: [B][B][2]. */
+int litho_kernels_phi(const litho_bank_t *bank, int plane, int k, double *h_phi_out);
+
+/* Host-only FP64 eigenpairs of one focus plane (the first half of
+ * litho_kernels_build, no device needed): the K_max largest eigenvalues of the
+ * TCC of Eq. 2 (descending) into h_lambda_out[K_max] and, if h_phi_out is not
+ * NULL, the unit-norm kernels Phi_k into h_phi_out[K_max][B][B][2] (centred
+ * band order, B = 2b + 1 as reported in *B_out).  optics->K is ignored;
+ * K_max must not exceed the number of source points (*n_source_out). */
+int litho_socs_host(const litho_optics_t *optics, int plane, int K_max, double *h_lambda_out,
+                    double *h_phi_out, int *B_out, int *n_source_out);
+
+/* Release the bank and every workspace it holds.  Waits for the device. NULL is ignored. */
+void litho_kernels_free(litho_bank_t *bank);
+
+/* Forward SOCS image, Eq. 4, for each focus plane of the bank.
+ *   d_mask:  [batch][n][n] mask values (the thin-mask transmission, 1 = clear).
+ *   K_use:   kernels used per plane, 1..K (the K_use largest).
+ *   d_image: [batch][n_focus][n][n] output.
+ *   prec:    LITHO_PREC_*.
+ * batch may be 0 (no work).  Asynchronous on hip_stream. */
+int litho_image(const litho_bank_t *bank, const float *d_mask, int batch, int K_use,
+                float *d_image, int prec, void *hip_stream);
+
+typedef struct litho_resist {
+  double slope;       /* a of the sigmoid resist (e.g. 50) */
+  double threshold;   /* t, relative to the open-frame intensity (e.g. 0.3) */
+} litho_resist_t;
+
+/* Forward image plus the ILT adjoint (mask gradient).
+ * Two modes:
+ *   fused loss  (d_target != NULL): Z = sigmoid(a (I - t)),
+ *                L = sum_planes sum_r (Z - T)^2 per clip,
+ *                G = dL/dI = 2 (Z - T) a Z (1 - Z); resist must be non-NULL.
+ *   VJP         (d_target == NULL): G = d_grad_image, [batch][n_focus][n][n].
+ * For each plane and kernel the coherent field E_k is recomputed (never
+ * stored) and correlated with G through the conjugate kernel:
+ *   dL/dm = sum_p sum_k 2 lambda_k Re IDFT( conj(Phi_k) DFT(G_p E_k) ).
+ *   d_image:    [batch][n_focus][n][n] or NULL (then not written).
+ *   d_loss:     device double [batch] or NULL (fused mode only).
+ *   d_grad_mask:[batch][n][n] output.
+ * Asynchronous on hip_stream. */
+int litho_image_grad(const litho_bank_t *bank, const float *d_mask, int batch, int K_use,
+                     const float *d_target, const litho_resist_t *resist,
+                     const float *d_grad_image, float *d_image, double *d_loss,
+                     float *d_grad_mask, int prec, void *hip_stream);
+
+/* Per-kernel device timing (tracing).  While enabled, every kernel launch is
+ * bracketed by HIP events on its own stream; litho_profile_read() waits for
+ * those events and returns, per kernel name, the launch count and the summed
+ * duration in milliseconds, then clears them.  Names are written as
+ * "name=count:total_ms;" into buf (truncated to cap bytes, NUL-terminated). */
+int litho_profile_enable(int on);
+int litho_profile_read(char *buf, size_t cap);
+
+/* ---------------------------------------------------------------- serving
+ * A persistent request loop (continuous batching): requests of mixed clip
+ * size arrive at any time, are admitted while their device footprint fits in
+ * hbm_budget bytes and a slot is free, run on that slot's own stream
+ * concurrently with other slots, and complete independently.  Banks stay
+ * resident for the life of the server (the caller keeps them alive). */
+typedef struct litho_server litho_server_t;
+
+typedef struct litho_serve_cfg {
+  size_t hbm_budget;   /* bytes of device memory requests may hold at once */
+  int max_slots;       /* concurrent requests on the device (streams), 1..64 */
+  int max_queue;       /* pending requests before submit returns LITHO_E_BUSY */
+} litho_serve_cfg_t;
+
+typedef struct litho_request {
+  int bank;            /* index into the server's banks */
+  int K_use;           /* kernels per plane, 1..K of that bank */
+  int mode;            /* 0 = image only, 1 = image + loss + gradient */
+  const float *h_mask;    /* [n][n] host, copied at submit */
+  const float *h_target;  /* [n][n] host (mode 1), copied at submit */
+  double slope, threshold; /* resist (mode 1) */
+} litho_request_t;
+
+typedef struct litho_result_info {
+  int status;          /* LITHO_OK or the error of the request */
+  int n, n_focus;
+  double loss;         /* mode 1 */
+  double t_submit_us;  /* library clock (monotonic, microseconds) */
+  double t_start_us;   /* admitted to a slot */
+  double t_done_us;    /* device work finished */
+} litho_result_info_t;
+
+/* Create a server over n_banks resident banks (the pointers are copied; the
+ * banks must outlive the server). */
+int litho_serve_create(litho_bank_t *const *banks, int n_banks, const litho_serve_cfg_t *cfg,
+                       litho_server_t **out);
+
+/* Queue a request; *ticket receives its id.  The mask/target are copied, so
+ * the caller may reuse them at once.  LITHO_E_NOMEM if the request can never
+ * fit hbm_budget, LITHO_E_BUSY if the queue is full. */
+int litho_serve_submit(litho_server_t *srv, const litho_request_t *req, uint64_t *ticket);
+
+/* Wait up to timeout_us (0 = do not wait, < 0 = forever) for a ticket.
+ * Returns LITHO_PENDING while running; on completion copies the image
+ * ([n_focus][n][n]) and, for mode 1, the gradient ([n][n]) into the host
+ * buffers (either may be NULL), fills *info and releases the ticket. */
+int litho_serve_poll(litho_server_t *srv, uint64_t ticket, float *h_image, float *h_grad,
+                     litho_result_info_t *info, int64_t timeout_us);
+
+/* Stop the loop, wait for in-flight work and free everything. NULL is ignored. */
+void litho_serve_destroy(litho_server_t *srv);
+
+/* Text of the last error on this thread ("" if none). */
+const char *litho_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LITHO_H */

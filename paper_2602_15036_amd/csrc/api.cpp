@@ -1,0 +1,507 @@
+// C ABI of the SOCS imaging library: banks, imaging, adjoint and tracing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bank.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "litho_internal.hpp"
+
+// ============================================================ errors
+namespace litho {
+namespace {
+thread_local std::string t_err;
+}
+void set_error(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+}
+void clear_error() { t_err.clear(); }
+const char *last_error() { return t_err.c_str(); }
+
+// ============================================================ tracing
+namespace {
+struct ProfRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+std::atomic<bool> g_prof{false};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_event_pool;
+thread_local hipEvent_t t_pending = nullptr;
+
+hipEvent_t take_event() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+void prof_begin(const char *name, hipStream_t s) {
+  (void)name;
+  t_pending = nullptr;
+  if (!g_prof.load(std::memory_order_relaxed)) return;
+  hipEvent_t e = take_event();
+  if (e && hipEventRecord(e, s) == hipSuccess) t_pending = e;
+}
+
+void prof_end(const char *name, hipStream_t s) {
+  if (!t_pending) return;
+  hipEvent_t e = take_event();
+  if (!e || hipEventRecord(e, s) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_recs.push_back({name, t_pending, e});
+  t_pending = nullptr;
+}
+
+// ============================================================ geometry helpers
+bool pow2_side(int n) { return n >= 64 && n <= 4096 && (n & (n - 1)) == 0; }
+
+}  // namespace litho
+
+using namespace litho;
+
+// ============================================================ bank
+static int upload_bank(litho_bank *bk) {
+  HostBank &h = bk->host;
+  bk->Bp = (h.B + kTileCols - 1) / kTileCols * kTileCols;
+  bk->nt = bk->Bp / kTileCols;
+  bk->Q = h.n;
+  LITHO_HIP_TRY(hipGetDevice(&bk->device));
+  const size_t per = size_t(bk->nt) * h.B * kTileCols;
+  std::vector<float2> tiles(size_t(h.n_focus) * h.K * per, make_float2(0.f, 0.f));
+  for (int p = 0; p < h.n_focus; ++p)
+    for (int k = 0; k < h.K; ++k) {
+      const double sl = std::sqrt(h.lambda[size_t(p) * h.K + k]);
+      const cd *ph = &h.phi[(size_t(p) * h.K + k) * h.B * h.B];
+      float2 *dst = &tiles[(size_t(p) * h.K + k) * per];
+      for (int r = 0; r < h.B; ++r)
+        for (int j = 0; j < h.B; ++j) {
+          const cd v = ph[size_t(r) * h.B + j] * sl;
+          dst[(size_t(j / kTileCols) * h.B + r) * kTileCols + (j % kTileCols)] =
+              make_float2(float(v.real()), float(v.imag()));
+        }
+    }
+  bk->phi_bytes = tiles.size() * sizeof(float2);
+  if (hipMalloc(&bk->d_phi, bk->phi_bytes) != hipSuccess) {
+    set_error("litho: cannot allocate %zu bytes for the kernel bank", bk->phi_bytes);
+    return LITHO_E_NOMEM;
+  }
+  LITHO_HIP_TRY(hipMemcpy(bk->d_phi, tiles.data(), bk->phi_bytes, hipMemcpyHostToDevice));
+  // Twiddle table exp(-2 pi i e / L), computed in FP64 and rounded once.
+  auto make_tw = [&](int L, float2 **out) -> int {
+    std::vector<float2> tw(L);
+    for (int e = 0; e < L; ++e) {
+      const double a = -2.0 * M_PI * double(e) / double(L);
+      tw[e] = make_float2(float(std::cos(a)), float(std::sin(a)));
+    }
+    if (hipMalloc(out, L * sizeof(float2)) != hipSuccess) {
+      set_error("litho: cannot allocate the twiddle table");
+      return LITHO_E_NOMEM;
+    }
+    LITHO_HIP_TRY(hipMemcpy(*out, tw.data(), L * sizeof(float2), hipMemcpyHostToDevice));
+    return LITHO_OK;
+  };
+  LITHO_TRY(make_tw(h.n, &bk->d_twN));
+  bk->d_twQ = bk->d_twN;
+  return LITHO_OK;
+}
+
+extern "C" int litho_kernels_build(const litho_optics_t *optics, litho_bank_t **out) {
+  clear_error();
+  if (!optics || !out) {
+    set_error("litho_kernels_build: NULL argument");
+    return LITHO_E_INVALID;
+  }
+  *out = nullptr;
+  if (!pow2_side(optics->n)) {
+    set_error("litho_kernels_build: grid side %d is not a power of two in [64, 4096]", optics->n);
+    return LITHO_E_UNSUPPORTED;
+  }
+  auto *bk = new litho_bank();
+  int rc = build_host_bank(*optics, bk->host);
+  if (rc == LITHO_OK) rc = upload_bank(bk);
+  if (rc != LITHO_OK) {
+    litho_kernels_free(bk);
+    return rc;
+  }
+  *out = bk;
+  return LITHO_OK;
+}
+
+extern "C" int litho_kernels_load(int n, int B, int K, int n_focus, const double *h_lambda, const double *h_phi,
+                                  litho_bank_t **out) {
+  clear_error();
+  if (!out || !h_lambda || !h_phi) {
+    set_error("litho_kernels_load: NULL argument");
+    return LITHO_E_INVALID;
+  }
+  *out = nullptr;
+  if (!pow2_side(n)) {
+    set_error("litho_kernels_load: grid side %d is not a power of two in [64, 4096]", n);
+    return LITHO_E_UNSUPPORTED;
+  }
+  if (B < 1 || (B % 2) == 0 || B > n || K < 1 || n_focus < 1 || n_focus > 8) {
+    set_error("litho_kernels_load: invalid sizes (B=%d K=%d n_focus=%d)", B, K, n_focus);
+    return LITHO_E_INVALID;
+  }
+  for (int i = 0; i < K * n_focus; ++i)
+    if (!(h_lambda[i] >= 0.0) || !std::isfinite(h_lambda[i])) {
+      set_error("litho_kernels_load: eigenvalue %d is negative or not finite", i);
+      return LITHO_E_INVALID;
+    }
+  auto *bk = new litho_bank();
+  HostBank &h = bk->host;
+  h.n = n; h.B = B; h.b = (B - 1) / 2; h.K = K; h.n_focus = n_focus; h.n_source = 0; h.R = 0.0;
+  h.lambda.assign(h_lambda, h_lambda + size_t(K) * n_focus);
+  h.phi.resize(size_t(n_focus) * K * B * B);
+  for (size_t i = 0; i < h.phi.size(); ++i) h.phi[i] = cd(h_phi[2 * i], h_phi[2 * i + 1]);
+  h.gap.assign(n_focus, 0.0);
+  int rc = upload_bank(bk);
+  if (rc != LITHO_OK) {
+    litho_kernels_free(bk);
+    return rc;
+  }
+  *out = bk;
+  return LITHO_OK;
+}
+
+extern "C" int litho_socs_host(const litho_optics_t *optics, int plane, int K_max, double *h_lambda_out,
+                               double *h_phi_out, int *B_out, int *n_source_out) {
+  clear_error();
+  if (!optics || !h_lambda_out || K_max < 1) {
+    set_error("litho_socs_host: invalid argument");
+    return LITHO_E_INVALID;
+  }
+  if (plane < 0 || plane >= optics->n_focus || !optics->focus_nm) {
+    set_error("litho_socs_host: plane %d outside the %d focus planes", plane, optics->n_focus);
+    return LITHO_E_INVALID;
+  }
+  litho_optics_t one = *optics;
+  one.n_focus = 1;
+  one.focus_nm = optics->focus_nm + plane;
+  one.K = K_max;
+  HostBank hb;
+  LITHO_TRY(build_host_bank(one, hb));
+  std::memcpy(h_lambda_out, hb.lambda.data(), size_t(K_max) * sizeof(double));
+  if (h_phi_out)
+    for (size_t i = 0; i < hb.phi.size(); ++i) {
+      h_phi_out[2 * i] = hb.phi[i].real();
+      h_phi_out[2 * i + 1] = hb.phi[i].imag();
+    }
+  if (B_out) *B_out = hb.B;
+  if (n_source_out) *n_source_out = hb.n_source;
+  return LITHO_OK;
+}
+
+extern "C" int litho_kernels_info(const litho_bank_t *bk, litho_bank_info_t *info) {
+  clear_error();
+  if (!bk || !info) {
+    set_error("litho_kernels_info: NULL argument");
+    return LITHO_E_INVALID;
+  }
+  info->n = bk->host.n;
+  info->b = bk->host.b;
+  info->B = bk->host.B;
+  info->K = bk->host.K;
+  info->n_focus = bk->host.n_focus;
+  info->n_source = bk->host.n_source;
+  info->inner_grid = bk->Q;
+  info->pupil_radius = bk->host.R;
+  info->device_bytes = bk->phi_bytes + size_t(bk->host.n) * sizeof(float2);
+  return LITHO_OK;
+}
+
+extern "C" int litho_kernels_eigenvalues(const litho_bank_t *bk, double *h_lambda_out) {
+  clear_error();
+  if (!bk || !h_lambda_out) {
+    set_error("litho_kernels_eigenvalues: NULL argument");
+    return LITHO_E_INVALID;
+  }
+  std::memcpy(h_lambda_out, bk->host.lambda.data(), bk->host.lambda.size() * sizeof(double));
+  return LITHO_OK;
+}
+
+extern "C" int litho_kernels_phi(const litho_bank_t *bk, int plane, int k, double *h_phi_out) {
+  clear_error();
+  if (!bk || !h_phi_out || plane < 0 || plane >= bk->host.n_focus || k < 0 || k >= bk->host.K) {
+    set_error("litho_kernels_phi: invalid argument");
+    return LITHO_E_INVALID;
+  }
+  const size_t BB = size_t(bk->host.B) * bk->host.B;
+  const cd *src = &bk->host.phi[(size_t(plane) * bk->host.K + k) * BB];
+  for (size_t i = 0; i < BB; ++i) {
+    h_phi_out[2 * i] = src[i].real();
+    h_phi_out[2 * i + 1] = src[i].imag();
+  }
+  return LITHO_OK;
+}
+
+extern "C" void litho_kernels_free(litho_bank_t *bk) {
+  if (!bk) return;
+  (void)hipDeviceSynchronize();
+  for (auto &kv : bk->ws)
+    if (kv.second.base) (void)hipFree(kv.second.base);
+  if (bk->d_twQ && bk->d_twQ != bk->d_twN) (void)hipFree(bk->d_twQ);
+  if (bk->d_twN) (void)hipFree(bk->d_twN);
+  if (bk->d_phi) (void)hipFree(bk->d_phi);
+  delete bk;
+}
+
+// ============================================================ workspace
+namespace litho {
+
+size_t workspace_limit_bytes() {
+  const char *e = std::getenv("LITHO_WORKSPACE_MB");
+  size_t mb = 8192;
+  if (e && *e) mb = size_t(std::strtoull(e, nullptr, 10));
+  return std::max<size_t>(mb, 1) << 20;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool fused) {
+  CallLayout L;
+  const HostBank &h = bk->host;
+  PassGeo &g = L.g;
+  g.N = h.n; g.Q = bk->Q; g.b = h.b; g.B = h.B; g.Bp = bk->Bp; g.nt = bk->nt;
+  g.K = K_use; g.Kbank = h.K; g.P = h.n_focus; g.dose = h.dose;
+  g.kper = 4;
+  g.KC = (K_use + g.kper - 1) / g.kper;
+  const int T = pass_threads(g.Q);
+  L.nblk = g.Q / (256 / T);
+  const size_t N = g.N, Q = g.Q;
+  L.b_S1 = align256(size_t(g.nt) * N * kTileCols * sizeof(float2));
+  L.b_Mh = align256(size_t(g.nt) * g.B * kTileCols * sizeof(float2));
+  L.b_Y = align256(size_t(K_use) * g.nt * Q * kTileCols * sizeof(float2));
+  L.b_G = (grad && fused) ? align256(N * N * sizeof(float)) : 0;
+  L.b_part = grad ? align256(size_t(g.P) * g.KC * g.nt * g.B * kTileCols * sizeof(double2)) : 0;
+  L.b_loss = (grad && fused) ? align256(size_t(g.P) * L.nblk * sizeof(double)) : 0;
+  const size_t per = L.b_S1 + L.b_Mh + L.b_Y + L.b_G + L.b_part + L.b_loss;
+  L.per_clip = per;
+  const size_t lim = workspace_limit_bytes();
+  L.chunk = int(std::max<size_t>(1, std::min<size_t>(size_t(batch), lim / per)));
+  return L;
+}
+
+int acquire_workspace(litho_bank *bk, hipStream_t s, size_t bytes, char **out) {
+  std::lock_guard<std::mutex> lk(bk->mu);
+  Workspace &w = bk->ws[s];
+  if (w.bytes < bytes) {
+    if (w.base) {
+      LITHO_HIP_TRY(hipStreamSynchronize(s));
+      LITHO_HIP_TRY(hipFree(w.base));
+      w.base = nullptr;
+      w.bytes = 0;
+    }
+    if (hipMalloc(&w.base, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      w.base = nullptr;
+      set_error("litho: cannot allocate a %zu byte workspace", bytes);
+      return LITHO_E_NOMEM;
+    }
+    w.bytes = bytes;
+  }
+  *out = static_cast<char *>(w.base);
+  return LITHO_OK;
+}
+
+// Forward (and optionally adjoint) over one chunk of clips.
+int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, int n, const float *target,
+              const float *grad_image, float *image, double *loss, float *grad_mask, bool grad, hipStream_t s,
+              double slope, double thr) {
+  PassGeo g = L.g;
+  g.slope = slope;
+  g.thr = thr;
+  char *p = ws;
+  auto *S1 = reinterpret_cast<float2 *>(p); p += L.b_S1 * n;
+  auto *Mh = reinterpret_cast<float2 *>(p); p += L.b_Mh * n;
+  auto *Y = reinterpret_cast<float2 *>(p); p += L.b_Y * n;
+  auto *G = reinterpret_cast<float *>(p); p += L.b_G * n;
+  auto *part = reinterpret_cast<double2 *>(p); p += L.b_part * n;
+  auto *lossp = reinterpret_cast<double *>(p);
+  const bool fused = target != nullptr;
+  const size_t NN = size_t(g.N) * g.N;
+  // Per-clip strides inside the chunk follow the per-clip block sizes.
+  LITHO_TRY(run_mask_spectrum(mask, S1, Mh, g, bk->d_twN, n, s));
+  for (int pl = 0; pl < g.P; ++pl) {
+    g.p = pl;
+    LITHO_TRY(run_pass_y_fwd(bk->d_phi, Mh, Y, g, bk->d_twQ, n, s));
+    LITHO_TRY(run_pass_x_fwd(Y, image, grad && fused ? target : nullptr, G, lossp, g, bk->d_twQ, n, s));
+    if (!grad) continue;
+    const float *Gp = fused ? G : grad_image + size_t(pl) * NN;
+    const size_t gstride = fused ? NN : size_t(g.P) * NN;
+    LITHO_TRY(run_pass_x_adj(Y, Gp, gstride, g, bk->d_twQ, n, s));
+    LITHO_TRY(run_pass_y_adj(Y, bk->d_phi, part, g, bk->d_twQ, n, s));
+  }
+  if (grad) {
+    LITHO_TRY(run_grad_finish(part, g.P * g.KC, S1, grad_mask, g, bk->d_twN, n, s));
+    if (fused && loss) LITHO_TRY(run_loss_reduce(lossp, g.P * L.nblk, loss, n, s));
+  }
+  return LITHO_OK;
+}
+
+}  // namespace litho
+
+static int check_call(const litho_bank *bk, const float *d_mask, int batch, int K_use, int prec,
+                      const char *who) {
+  if (!bk) {
+    set_error("%s: NULL bank", who);
+    return LITHO_E_INVALID;
+  }
+  if (batch < 0) {
+    set_error("%s: negative batch", who);
+    return LITHO_E_INVALID;
+  }
+  if (batch > 0 && !d_mask) {
+    set_error("%s: NULL mask", who);
+    return LITHO_E_INVALID;
+  }
+  if (K_use < 1 || K_use > bk->host.K) {
+    set_error("%s: K_use=%d outside 1..%d", who, K_use, bk->host.K);
+    return LITHO_E_INVALID;
+  }
+  if (prec != LITHO_PREC_FP32) {
+    set_error("%s: precision mode %d is not supported", who, prec);
+    return LITHO_E_UNSUPPORTED;
+  }
+  return LITHO_OK;
+}
+
+namespace litho {
+
+// Per-clip strides of the workspace sections are laid out [section][clip],
+// so the kernels see dense per-clip arrays.  run_chunk() expects exactly that.
+int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, const float *d_target,
+                    const litho_resist_t *resist, const float *d_grad_image, float *d_image, double *d_loss,
+                    float *d_grad_mask, bool grad, hipStream_t s) {
+  if (batch == 0) return LITHO_OK;
+  const bool fused = d_target != nullptr;
+  CallLayout L = plan_call(bk, batch, K_use, grad, fused);
+  char *ws = nullptr;
+  LITHO_TRY(acquire_workspace(bk, s, L.per_clip * size_t(L.chunk), &ws));
+  const size_t NN = size_t(bk->host.n) * bk->host.n;
+  const int P = bk->host.n_focus;
+  for (int c0 = 0; c0 < batch; c0 += L.chunk) {
+    const int n = std::min(L.chunk, batch - c0);
+    LITHO_TRY(run_chunk(bk, L, ws, d_mask + size_t(c0) * NN, n, fused ? d_target + size_t(c0) * NN : nullptr,
+                        d_grad_image ? d_grad_image + size_t(c0) * P * NN : nullptr,
+                        d_image ? d_image + size_t(c0) * P * NN : nullptr, d_loss ? d_loss + c0 : nullptr,
+                        d_grad_mask ? d_grad_mask + size_t(c0) * NN : nullptr, grad, s,
+                        resist ? resist->slope : 0.0, resist ? resist->threshold : 0.0));
+  }
+  return LITHO_OK;
+}
+
+}  // namespace litho
+
+extern "C" int litho_image(const litho_bank_t *bank, const float *d_mask, int batch, int K_use, float *d_image,
+                           int prec, void *hip_stream) {
+  clear_error();
+  LITHO_TRY(check_call(bank, d_mask, batch, K_use, prec, "litho_image"));
+  if (batch > 0 && !d_image) {
+    set_error("litho_image: NULL image");
+    return LITHO_E_INVALID;
+  }
+  return image_grad_impl(const_cast<litho_bank *>(bank), d_mask, batch, K_use, nullptr, nullptr, nullptr,
+                         d_image, nullptr, nullptr, false, static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" int litho_image_grad(const litho_bank_t *bank, const float *d_mask, int batch, int K_use,
+                                const float *d_target, const litho_resist_t *resist, const float *d_grad_image,
+                                float *d_image, double *d_loss, float *d_grad_mask, int prec, void *hip_stream) {
+  clear_error();
+  LITHO_TRY(check_call(bank, d_mask, batch, K_use, prec, "litho_image_grad"));
+  if (batch > 0 && !d_grad_mask) {
+    set_error("litho_image_grad: NULL gradient output");
+    return LITHO_E_INVALID;
+  }
+  if (d_target && !resist) {
+    set_error("litho_image_grad: a target needs resist parameters");
+    return LITHO_E_INVALID;
+  }
+  if (!d_target && !d_grad_image && batch > 0) {
+    set_error("litho_image_grad: give either a target (fused loss) or dL/dI (VJP)");
+    return LITHO_E_INVALID;
+  }
+  if (d_target && d_grad_image) {
+    set_error("litho_image_grad: target and dL/dI are exclusive");
+    return LITHO_E_INVALID;
+  }
+  if (d_loss && !d_target) {
+    set_error("litho_image_grad: the loss exists only in fused mode");
+    return LITHO_E_INVALID;
+  }
+  return image_grad_impl(const_cast<litho_bank *>(bank), d_mask, batch, K_use, d_target, resist, d_grad_image,
+                         d_image, d_loss, d_grad_mask, true, static_cast<hipStream_t>(hip_stream));
+}
+
+// ============================================================ tracing ABI
+extern "C" int litho_profile_enable(int on) {
+  clear_error();
+  g_prof.store(on != 0);
+  return LITHO_OK;
+}
+
+extern "C" int litho_profile_read(char *buf, size_t cap) {
+  clear_error();
+  std::vector<ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs.swap(g_recs);
+  }
+  std::map<std::string, std::pair<long, double>> agg;
+  int rc = LITHO_OK;
+  for (auto &r : recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      set_error("litho_profile_read: event query failed");
+      rc = LITHO_E_HIP;
+    }
+    auto &a = agg[r.name];
+    a.first += 1;
+    a.second += ms;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &r : recs) {
+      g_event_pool.push_back(r.a);
+      g_event_pool.push_back(r.b);
+    }
+  }
+  std::string s;
+  char tmp[160];
+  for (auto &kv : agg) {
+    snprintf(tmp, sizeof tmp, "%s=%ld:%.6f;", kv.first.c_str(), kv.second.first, kv.second.second);
+    s += tmp;
+  }
+  if (buf && cap) {
+    const size_t n = std::min(cap - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = '\0';
+  }
+  return rc;
+}
+
+extern "C" const char *litho_last_error(void) { return last_error(); }

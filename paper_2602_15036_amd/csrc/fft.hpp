@@ -1,0 +1,323 @@
+// Device FFT building blocks for gfx950 (wave64).
+//
+// A length-L transform is computed by T cooperating threads, each holding
+// E = L / T complex values in registers.  Thread t always holds the elements
+// at positions t + T*i (i = 0..E-1): on entry those are the inputs in natural
+// order, on exit the outputs in natural order.  The passes follow the
+// Stockham autosort scheme (each radix-R pass reads elements j + r L/R and
+// writes the butterfly outputs to (j / s) s R + (j mod s) + r s, s being the
+// product of the earlier radices), so no bit reversal is needed; between
+// passes the values are exchanged through LDS.  With the t + T*i register
+// layout the last pass writes exactly the positions its thread holds, so a
+// transform of P passes needs P - 1 LDS exchanges.
+//
+// Twiddles come from a table tw[e] = exp(-2 pi i e / L) computed on the host in
+// FP64 and rounded once to FP32 (no device sin/cos, no recurrences).  The
+// small in-register DFTs use exact radix-2/4 forms, radix-3/5 forms with
+// FP64-rounded constants, Good-Thomas splits for coprime composites and a
+// Cooley-Tukey split with constant twiddles for 8 and 16.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace litho {
+namespace dev {
+
+typedef float2 cf;
+
+__device__ __forceinline__ cf cmake(float x, float y) { return make_float2(x, y); }
+__device__ __forceinline__ cf cadd(cf a, cf b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cf csub(cf a, cf b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cf cscale(cf a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ cf cmul(cf a, cf b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ cf cconj(cf a) { return make_float2(a.x, -a.y); }
+// a * conj(b)
+__device__ __forceinline__ cf cmulc(cf a, cf b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float cabs2(cf a) { return a.x * a.x + a.y * a.y; }
+// a * (DIR * i):  i (x + iy) = -y + ix
+template <int DIR>
+__device__ __forceinline__ cf cmul_i(cf a) {
+  return DIR > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// cos / sin of 2 pi m / 16, m = 0..15 (exact values rounded to float).
+__device__ constexpr float kCos16[16] = {
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+    0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+    -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+    0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+__device__ constexpr float kSin16[16] = {
+    0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+    0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+    -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f};
+
+// a * exp(DIR * 2 pi i m / 16) with the trivial angles folded at compile time.
+template <int M, int DIR>
+__device__ __forceinline__ cf twiddle16(cf a) {
+  constexpr int m = ((M % 16) + 16) % 16;
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (m == 4) {
+    return cmul_i<DIR>(a);
+  } else if constexpr (m == 8) {
+    return make_float2(-a.x, -a.y);
+  } else if constexpr (m == 12) {
+    return cmul_i<-DIR>(a);
+  } else {
+    const float c = kCos16[m];
+    const float s = DIR > 0 ? kSin16[m] : -kSin16[m];
+    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+// ------------------------------------------------------------------ small DFTs
+// Dft<R, DIR>::run(v): in-place X[k] = sum_n v[n] exp(DIR 2 pi i n k / R).
+template <int R, int DIR>
+struct Dft;
+
+template <int DIR>
+struct Dft<1, DIR> {
+  __device__ __forceinline__ static void run(cf *) {}
+};
+
+template <int DIR>
+struct Dft<2, DIR> {
+  __device__ __forceinline__ static void run(cf *v) {
+    const cf a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+  }
+};
+
+template <int DIR>
+struct Dft<3, DIR> {
+  __device__ __forceinline__ static void run(cf *v) {
+    constexpr float s3 = 0.86602540378443865f;  // sin(2 pi / 3)
+    const cf t1 = cadd(v[1], v[2]);
+    const cf t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+    const cf t3 = cmul_i<DIR>(cscale(csub(v[1], v[2]), s3));
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(t2, t3);
+    v[2] = csub(t2, t3);
+  }
+};
+
+template <int DIR>
+struct Dft<4, DIR> {
+  __device__ __forceinline__ static void run(cf *v) {
+    const cf a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    const cf c = cadd(v[1], v[3]), d = cmul_i<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, d);
+    v[3] = csub(b, d);
+  }
+};
+
+template <int DIR>
+struct Dft<5, DIR> {
+  __device__ __forceinline__ static void run(cf *v) {
+    constexpr float c1 = 0.30901699437494742f;   // cos(2 pi / 5)
+    constexpr float c2 = -0.80901699437494742f;  // cos(4 pi / 5)
+    constexpr float s1 = 0.95105651629515357f;   // sin(2 pi / 5)
+    constexpr float s2 = 0.58778525229247313f;   // sin(4 pi / 5)
+    const cf a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const cf a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    const cf x0 = v[0];
+    const cf p1 = make_float2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+    const cf p2 = make_float2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+    const cf q1 = cmul_i<DIR>(make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+    const cf q2 = cmul_i<DIR>(make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+    v[0] = cadd(x0, cadd(a1, a2));
+    v[1] = cadd(p1, q1);
+    v[4] = csub(p1, q1);
+    v[2] = cadd(p2, q2);
+    v[3] = csub(p2, q2);
+  }
+};
+
+constexpr int ct_gcd(int a, int b) { return b == 0 ? a : ct_gcd(b, a % b); }
+constexpr int ct_inv_mod(int a, int m) {  // a^-1 mod m for gcd(a, m) = 1, m >= 1
+  int r = 0;
+  for (int x = 0; x < m; ++x)
+    if ((a * x) % m == 1 % m) r = x;
+  return r;
+}
+
+// Good-Thomas split R = A * B, gcd(A, B) = 1: no twiddles.
+// input n = (B n1 + A n2) mod R, output k = CRT(k1 mod A, k2 mod B).
+template <int A, int B, int DIR>
+struct DftPfa {
+  static_assert(ct_gcd(A, B) == 1, "coprime factors required");
+  __device__ __forceinline__ static void run(cf *v) {
+    constexpr int R = A * B;
+    cf t[B][A];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2)
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) t[n2][n1] = v[(B * n1 + A * n2) % R];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) Dft<A, DIR>::run(t[n2]);
+    cf u[A][B];
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1)
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) u[k1][n2] = t[n2][k1];
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) Dft<B, DIR>::run(u[k1]);
+    constexpr int eA = B * ct_inv_mod(B % A, A);
+    constexpr int eB = A * ct_inv_mod(A % B, B);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1)
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) v[(k1 * eA + k2 * eB) % R] = u[k1][k2];
+  }
+};
+
+// Cooley-Tukey split R = A * B (R divides 16): n = B n1 + n2, k = k1 + A k2,
+// twiddle exp(DIR 2 pi i n2 k1 / R) between the A-point and B-point stages.
+template <int A, int B, int DIR>
+struct DftCt {
+  __device__ __forceinline__ static void run(cf *v) {
+    constexpr int R = A * B;
+    static_assert(16 % R == 0, "constant twiddles cover divisors of 16");
+    cf t[B][A];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) t[n2][n1] = v[B * n1 + n2];
+      Dft<A, DIR>::run(t[n2]);
+    }
+    cf u[A][B];
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) {
+        const int m = (n2 * k1) * (16 / R);
+        // m is a compile-time constant after unrolling
+        u[k1][n2] = t[n2][k1];
+        switch (m) {  // folded by the compiler
+          case 0: break;
+          case 1: u[k1][n2] = twiddle16<1, DIR>(u[k1][n2]); break;
+          case 2: u[k1][n2] = twiddle16<2, DIR>(u[k1][n2]); break;
+          case 3: u[k1][n2] = twiddle16<3, DIR>(u[k1][n2]); break;
+          case 4: u[k1][n2] = twiddle16<4, DIR>(u[k1][n2]); break;
+          case 5: u[k1][n2] = twiddle16<5, DIR>(u[k1][n2]); break;
+          case 6: u[k1][n2] = twiddle16<6, DIR>(u[k1][n2]); break;
+          case 7: u[k1][n2] = twiddle16<7, DIR>(u[k1][n2]); break;
+          case 8: u[k1][n2] = twiddle16<8, DIR>(u[k1][n2]); break;
+          case 9: u[k1][n2] = twiddle16<9, DIR>(u[k1][n2]); break;
+          case 10: u[k1][n2] = twiddle16<10, DIR>(u[k1][n2]); break;
+          case 11: u[k1][n2] = twiddle16<11, DIR>(u[k1][n2]); break;
+          case 12: u[k1][n2] = twiddle16<12, DIR>(u[k1][n2]); break;
+          case 13: u[k1][n2] = twiddle16<13, DIR>(u[k1][n2]); break;
+          case 14: u[k1][n2] = twiddle16<14, DIR>(u[k1][n2]); break;
+          default: u[k1][n2] = twiddle16<15, DIR>(u[k1][n2]); break;
+        }
+      }
+      Dft<B, DIR>::run(u[k1]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1)
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = u[k1][k2];
+  }
+};
+
+template <int DIR> struct Dft<6, DIR> : DftPfa<2, 3, DIR> {};
+template <int DIR> struct Dft<8, DIR> : DftCt<2, 4, DIR> {};
+template <int DIR> struct Dft<10, DIR> : DftPfa<2, 5, DIR> {};
+template <int DIR> struct Dft<12, DIR> : DftPfa<4, 3, DIR> {};
+template <int DIR> struct Dft<16, DIR> : DftCt<4, 4, DIR> {};
+template <int DIR> struct Dft<20, DIR> : DftPfa<4, 5, DIR> {};
+
+// ------------------------------------------------------------------ plans
+template <int... Rs>
+struct Radices {};
+
+// FftPlan<L>: threads per transform T and the radix sequence (each radix must
+// divide E = L / T; their product is L).
+template <int L>
+struct FftPlan;
+template <> struct FftPlan<64> { static constexpr int T = 8; using R = Radices<8, 8>; };
+template <> struct FftPlan<128> { static constexpr int T = 8; using R = Radices<16, 8>; };
+template <> struct FftPlan<256> { static constexpr int T = 16; using R = Radices<16, 16>; };
+template <> struct FftPlan<512> { static constexpr int T = 32; using R = Radices<16, 8, 4>; };
+template <> struct FftPlan<1024> { static constexpr int T = 64; using R = Radices<16, 16, 4>; };
+template <> struct FftPlan<2048> { static constexpr int T = 64; using R = Radices<16, 16, 8>; };
+template <> struct FftPlan<4096> { static constexpr int T = 128; using R = Radices<16, 16, 16>; };
+
+// LDS index with one pad slot every 16 complex values (breaks the power-of-two
+// strides of the Stockham scatter).
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+template <int L>
+constexpr int lds_len() { return L + L / 16; }
+
+// One Stockham pass of radix R after passes whose radices multiply to S.
+template <int L, int T, int DIR, int R, int S, bool LAST>
+__device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ buf, int t,
+                                              const cf *__restrict__ tw) {
+  constexpr int E = L / T;
+  constexpr int NB = E / R;
+  static_assert(E % R == 0, "radix must divide the per-thread count");
+#pragma unroll
+  for (int mb = 0; mb < NB; ++mb) {
+    const int j = t + T * mb;
+    cf u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = v[mb + r * NB];
+    if constexpr (S > 1) {
+      const int k = j % S;
+      constexpr int step = L / (S * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cf w = tw[k * r * step];
+        if constexpr (DIR > 0) w.y = -w.y;
+        u[r] = cmul(u[r], w);
+      }
+    }
+    Dft<R, DIR>::run(u);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[mb + r * NB] = u[r];
+    } else {
+      const int base = (j / S) * S * R + (j % S);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lpad(base + r * S)] = u[r];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = buf[lpad(t + T * i)];
+    __syncthreads();
+  }
+}
+
+template <int L, int T, int DIR, int S, int R, int... Rest>
+__device__ __forceinline__ void run_passes(cf (&v)[L / T], cf *buf, int t, const cf *tw) {
+  stockham_pass<L, T, DIR, R, S, sizeof...(Rest) == 0>(v, buf, t, tw);
+  if constexpr (sizeof...(Rest) > 0) run_passes<L, T, DIR, S * R, Rest...>(v, buf, t, tw);
+}
+
+template <int L, int DIR, int... Rs>
+__device__ __forceinline__ void fft_impl(cf (&v)[L / FftPlan<L>::T], cf *buf, int t, const cf *tw,
+                                         Radices<Rs...>) {
+  run_passes<L, FftPlan<L>::T, DIR, 1, Rs...>(v, buf, t, tw);
+}
+
+// In-register FFT of length L (DIR = -1 forward, +1 inverse, unnormalised).
+// All threads of the block must call it (it contains block barriers).
+// buf: this transform's LDS region of lds_len<L>() complex values.
+template <int L, int DIR>
+__device__ __forceinline__ void fft(cf (&v)[L / FftPlan<L>::T], cf *buf, int t, const cf *tw) {
+  fft_impl<L, DIR>(v, buf, t, tw, typename FftPlan<L>::R{});
+}
+
+}  // namespace dev
+}  // namespace litho

@@ -1,0 +1,239 @@
+"""Python binding of liblitho.so (argument marshalling only).
+
+Every step of the imaging path runs in the HIP library; this module turns
+torch CUDA tensors (device memory) and the current torch stream into the raw
+pointers of the C ABI in include/litho.h and turns error codes into
+exceptions.  There is no CPU fallback: importing this module fails when the
+library is missing, and every call fails when it returns an error.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # imported first so the library binds to torch's HIP runtime
+
+from . import _abi as A
+
+_lib = A.load_library()
+
+
+class LithoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{A.ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise LithoError(rc, f"{what}: {_lib.litho_last_error().decode()}")
+    return rc
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_ptr(t: Optional[torch.Tensor], what: str, dtype=torch.float32):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+SOURCE_KINDS = {"annular": A.LITHO_SRC_ANNULAR, "dipole_x": A.LITHO_SRC_DIPOLE_X}
+
+
+class Bank:
+    """A device-resident SOCS kernel bank (Eqs. 2-3), one plane per focus value."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+        info = A.BankInfo()
+        _check(_lib.litho_kernels_info(self._h, C.byref(info)), "litho_kernels_info")
+        self.n, self.b, self.B, self.K = info.n, info.b, info.B, info.K
+        self.n_focus, self.n_source = info.n_focus, info.n_source
+        self.inner_grid, self.pupil_radius = info.inner_grid, info.pupil_radius
+        self.device_bytes = info.device_bytes
+
+    @classmethod
+    def build(cls, n: int, pixel_nm: float, na: float, source: str = "annular",
+              sigma_in: float = 0.5, sigma_out: float = 0.8, wavelength_nm: float = 13.5,
+              source_grid: int = 15, focus_nm: Sequence[float] = (0.0,), K: int = 8,
+              dose: float = 1.0) -> "Bank":
+        focus = (C.c_double * len(focus_nm))(*[float(f) for f in focus_nm])
+        o = A.Optics(n=n, pixel_nm=pixel_nm, wavelength_nm=wavelength_nm, na=na,
+                     source_kind=SOURCE_KINDS[source], source_grid=source_grid,
+                     sigma_in=sigma_in, sigma_out=sigma_out, n_focus=len(focus_nm),
+                     focus_nm=C.cast(focus, C.POINTER(C.c_double)), K=K, dose=dose)
+        h = C.c_void_p()
+        _check(_lib.litho_kernels_build(C.byref(o), C.byref(h)), "litho_kernels_build")
+        return cls(h)
+
+    @classmethod
+    def from_spec(cls, spec, K: Optional[int] = None) -> "Bank":
+        """Build from any object with the fields of an optics spec (n, pixel_nm, ...)."""
+        return cls.build(n=spec.n, pixel_nm=spec.pixel_nm, na=spec.na, source=spec.source,
+                         sigma_in=spec.sigma_in, sigma_out=spec.sigma_out,
+                         wavelength_nm=spec.wavelength_nm, source_grid=spec.source_grid,
+                         focus_nm=tuple(spec.focus_nm), K=spec.K if K is None else K)
+
+    @classmethod
+    def load(cls, n: int, lam: np.ndarray, phi: np.ndarray) -> "Bank":
+        """Load eigenpairs: lam [P, K], phi [P, K, B, B] complex (centred band)."""
+        lam = np.ascontiguousarray(np.atleast_2d(lam), dtype=np.float64)
+        phi = np.asarray(phi)
+        if phi.ndim == 3:
+            phi = phi[None]
+        P, K, B, _ = phi.shape
+        ph = np.ascontiguousarray(np.stack([phi.real, phi.imag], axis=-1), dtype=np.float64)
+        h = C.c_void_p()
+        _check(_lib.litho_kernels_load(n, B, K, P, lam.ctypes.data_as(C.POINTER(C.c_double)),
+                                       ph.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)),
+               "litho_kernels_load")
+        return cls(h)
+
+    def eigenvalues(self) -> np.ndarray:
+        out = np.zeros((self.n_focus, self.K))
+        _check(_lib.litho_kernels_eigenvalues(self._h, out.ctypes.data_as(C.POINTER(C.c_double))),
+               "litho_kernels_eigenvalues")
+        return out
+
+    def phi(self, plane: int, k: int) -> np.ndarray:
+        out = np.zeros((self.B, self.B, 2))
+        _check(_lib.litho_kernels_phi(self._h, plane, k, out.ctypes.data_as(C.POINTER(C.c_double))),
+               "litho_kernels_phi")
+        return out[..., 0] + 1j * out[..., 1]
+
+    @property
+    def handle(self) -> C.c_void_p:
+        if self._h is None:
+            raise ValueError("bank has been freed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.litho_kernels_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _mask_batch(mask: torch.Tensor, n: int) -> torch.Tensor:
+    if mask.dim() == 2:
+        mask = mask[None]
+    if mask.dim() != 3 or mask.shape[-1] != n or mask.shape[-2] != n:
+        raise ValueError(f"mask must be [batch, {n}, {n}], got {tuple(mask.shape)}")
+    return mask
+
+
+def image(bank: Bank, mask: torch.Tensor, K_use: Optional[int] = None,
+          out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """SOCS aerial image (Eq. 4): [batch, n_focus, n, n] float32 on the mask's device."""
+    mask = _mask_batch(mask, bank.n)
+    batch = mask.shape[0]
+    K_use = bank.K if K_use is None else int(K_use)
+    if out is None:
+        out = torch.empty((batch, bank.n_focus, bank.n, bank.n), device=mask.device, dtype=torch.float32)
+    _check(_lib.litho_image(bank.handle, _dev_ptr(mask, "mask"), batch, K_use, _dev_ptr(out, "image"),
+                            A.LITHO_PREC_FP32, C.c_void_p(_stream_handle(stream))), "litho_image")
+    return out
+
+
+def image_grad(bank: Bank, mask: torch.Tensor, target: Optional[torch.Tensor] = None,
+               slope: float = 50.0, threshold: float = 0.3, grad_image: Optional[torch.Tensor] = None,
+               K_use: Optional[int] = None, want_image: bool = True, stream=None):
+    """Image, loss and mask gradient (fused sigmoid-L2 loss) or a VJP with dL/dI.
+
+    Returns (image or None, loss [batch] float64 or None, grad [batch, n, n]).
+    """
+    mask = _mask_batch(mask, bank.n)
+    batch = mask.shape[0]
+    K_use = bank.K if K_use is None else int(K_use)
+    dev = mask.device
+    img = torch.empty((batch, bank.n_focus, bank.n, bank.n), device=dev, dtype=torch.float32) \
+        if want_image else None
+    grad = torch.empty((batch, bank.n, bank.n), device=dev, dtype=torch.float32)
+    loss = None
+    resist = None
+    if target is not None:
+        target = _mask_batch(target, bank.n)
+        loss = torch.empty((batch,), device=dev, dtype=torch.float64)
+        resist = A.Resist(slope=slope, threshold=threshold)
+    if grad_image is not None and grad_image.shape != (batch, bank.n_focus, bank.n, bank.n):
+        raise ValueError("grad_image must be [batch, n_focus, n, n]")
+    _check(_lib.litho_image_grad(
+        bank.handle, _dev_ptr(mask, "mask"), batch, K_use, _dev_ptr(target, "target"),
+        C.byref(resist) if resist is not None else None, _dev_ptr(grad_image, "grad_image"),
+        _dev_ptr(img, "image"), _dev_ptr(loss, "loss", torch.float64), _dev_ptr(grad, "grad"),
+        A.LITHO_PREC_FP32, C.c_void_p(_stream_handle(stream))), "litho_image_grad")
+    return img, loss, grad
+
+
+class LithoImage(torch.autograd.Function):
+    """I = SOCS image of the mask; backward is the adjoint with dL/dI (E_k recomputed)."""
+
+    @staticmethod
+    def forward(ctx, mask, bank: Bank, K_use: Optional[int] = None):
+        ctx.bank, ctx.K_use = bank, K_use
+        ctx.save_for_backward(mask)
+        return image(bank, mask.contiguous(), K_use)
+
+    @staticmethod
+    def backward(ctx, g_image):
+        (mask,) = ctx.saved_tensors
+        _, _, g = image_grad(ctx.bank, mask.contiguous(), grad_image=g_image.contiguous().float(),
+                             K_use=ctx.K_use, want_image=False)
+        return g.view_as(mask), None, None
+
+
+class LithoILTLoss(torch.autograd.Function):
+    """Per-clip ILT loss sum_planes sum_r (sigmoid(a (I - t)) - T)^2 with the fused adjoint.
+
+    The forward call computes the loss and dL/dm together; backward scales the
+    stored gradient by the incoming per-clip weights.
+    """
+
+    @staticmethod
+    def forward(ctx, mask, target, bank: Bank, K_use: Optional[int] = None, slope: float = 50.0,
+                threshold: float = 0.3):
+        _, loss, grad = image_grad(bank, mask.contiguous(), target=target.contiguous(), slope=slope,
+                                   threshold=threshold, K_use=K_use, want_image=False)
+        ctx.save_for_backward(grad)
+        ctx.mask_shape = mask.shape
+        return loss
+
+    @staticmethod
+    def backward(ctx, g_loss):
+        (grad,) = ctx.saved_tensors
+        w = g_loss.to(torch.float32).view(-1, 1, 1)
+        return (grad * w).view(ctx.mask_shape), None, None, None, None, None
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(_lib.litho_profile_enable(1 if on else 0), "litho_profile_enable")
+
+
+def profile_read() -> dict:
+    """{kernel name: (launch count, total milliseconds)} since the last read."""
+    buf = C.create_string_buffer(1 << 16)
+    _check(_lib.litho_profile_read(buf, len(buf)), "litho_profile_read")
+    out = {}
+    for item in buf.value.decode().split(";"):
+        if not item:
+            continue
+        name, rest = item.split("=")
+        cnt, ms = rest.split(":")
+        out[name] = (int(cnt), float(ms))
+    return out

@@ -1,0 +1,103 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, validates arguments on the host, and its FP64 host bank builder agrees
+with the oracle's eigendecomposition."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from paper_2602_15036_amd import _abi as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "litho.h")
+
+
+@pytest.fixture(scope="module")
+def clib():
+    return A.load_library()
+
+
+def test_library_exports_every_header_symbol(clib):
+    names = A.header_symbols(HEADER)
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(clib, n), n
+    assert set(names) == set(A.SIGNATURES), set(names) ^ set(A.SIGNATURES)
+
+
+def _optics(spec, K=None, focus=None):
+    focus = tuple(spec.focus_nm if focus is None else focus)
+    arr = (C.c_double * len(focus))(*focus)
+    o = A.Optics(n=spec.n, pixel_nm=spec.pixel_nm, wavelength_nm=spec.wavelength_nm, na=spec.na,
+                 source_kind=0 if spec.source == "annular" else 1, source_grid=spec.source_grid,
+                 sigma_in=spec.sigma_in, sigma_out=spec.sigma_out, n_focus=len(focus),
+                 focus_nm=C.cast(arr, C.POINTER(C.c_double)), K=spec.K if K is None else K, dose=1.0)
+    o._keep = arr
+    return o
+
+
+def test_host_argument_validation(clib):
+    h = C.c_void_p()
+    assert clib.litho_kernels_build(None, C.byref(h)) == A.LITHO_E_INVALID
+    assert b"NULL" in clib.litho_last_error()
+    o = _optics(W.CONFIG1.with_(n=100))
+    assert clib.litho_kernels_build(C.byref(o), C.byref(h)) == A.LITHO_E_UNSUPPORTED
+    o = _optics(W.CONFIG1, K=61)            # rank bound is 60 source points
+    assert clib.litho_kernels_build(C.byref(o), C.byref(h)) == A.LITHO_E_INVALID
+    assert b"rank" in clib.litho_last_error()
+    o = _optics(W.CONFIG1)
+    o.sigma_out = 1.5
+    assert clib.litho_kernels_build(C.byref(o), C.byref(h)) == A.LITHO_E_INVALID
+    lam = (C.c_double * 1)(1.0)
+    phi = (C.c_double * 2)(1.0, 0.0)
+    assert clib.litho_kernels_load(64, 2, 1, 1, lam, phi, C.byref(h)) == A.LITHO_E_INVALID  # even B
+    assert clib.litho_image(None, None, 1, 1, None, 0, None) == A.LITHO_E_INVALID
+    assert clib.litho_image_grad(None, None, 1, 1, None, None, None, None, None, None, 0, None) \
+        == A.LITHO_E_INVALID
+    assert clib.litho_serve_poll(None, 1, None, None, None, 0) < 0
+    clib.litho_kernels_free(None)
+    clib.litho_serve_destroy(None)
+
+
+def _host_socs(clib, spec, plane, K):
+    o = _optics(spec)
+    lam = np.zeros(K)
+    b, B, _ = O.band_geometry(spec)
+    phi = np.zeros((K, B, B, 2))
+    Bo = C.c_int()
+    ns = C.c_int()
+    rc = clib.litho_socs_host(C.byref(o), plane, K, lam.ctypes.data_as(C.POINTER(C.c_double)),
+                              phi.ctypes.data_as(C.POINTER(C.c_double)), C.byref(Bo), C.byref(ns))
+    assert rc == A.LITHO_OK, clib.litho_last_error()
+    assert Bo.value == B and ns.value == 60
+    return lam, phi[..., 0] + 1j * phi[..., 1]
+
+
+@pytest.mark.parametrize("spec,plane", [(W.CONFIG1, 0), (W.fd_clip_optics(64), 0),
+                                        (W.fd_clip_optics(64), 2), (W.CONFIG2.with_(n=256), 0)])
+def test_host_bank_matches_oracle(clib, spec, plane):
+    K = 24 if spec.K > 8 else 8
+    lam_c, phi_c = _host_socs(clib, spec, plane, K)
+    F = spec.focus_nm[plane]
+    lam_o, phi_o = O.socs_kernels(spec, F, K=K)
+    assert np.abs(lam_c - lam_o).max() < 1e-11 * lam_o[0]
+    # eigenvectors agree up to phase and rotations inside degenerate pairs:
+    # compare the projector onto the kept subspace, weighted by lambda
+    fc = phi_c.reshape(K, -1)
+    fo = phi_o.reshape(K, -1)
+    Pc = (fc.T * lam_c) @ fc.conj()
+    Po = (fo.T * lam_o) @ fo.conj()
+    assert np.abs(Pc - Po).max() < 1e-10 * lam_o[0]
+    assert np.abs(np.linalg.norm(fc, axis=1) - 1).max() < 1e-12
+
+
+def test_host_bank_full_spectrum_sum_matches_trace(clib):
+    spec = W.CONFIG1.with_(n=64)
+    lam, _ = _host_socs(clib, spec, 0, 60)
+    lam_o, _ = O.socs_kernels(spec, 0.0, K=60, route="gram")
+    assert abs(lam.sum() - lam_o.sum()) < 1e-10 * lam_o.sum()
+    assert lam.min() > 0
+    assert np.all(np.diff(lam) <= 1e-12 * lam[0])

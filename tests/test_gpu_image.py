@@ -1,0 +1,126 @@
+"""GPU parity of the forward SOCS image against the FP64 oracle (through the C ABI).
+
+Gate (FP32 path): relative L2 error <= 1e-5 against the oracle's FP64 image.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2602_15036_amd import litho
+    return litho
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def test_config1_parity_with_built_bank(L):
+    spec = W.CONFIG1
+    bank = L.Bank.from_spec(spec)
+    masks = np.stack([W.manhattan_mask(128, s) for s in range(8)])
+    img = L.image(bank, dev(masks)).cpu().numpy()
+    assert img.shape == (8, 1, 128, 128)
+    lam, phi = O.socs_kernels(spec, 0.0, K=8)
+    for i in range(8):
+        ref = O.image(masks[i], lam, phi)
+        assert rel_l2(img[i, 0], ref) < TOL, i
+
+
+def test_config1_parity_with_oracle_bank(L):
+    spec = W.CONFIG1
+    lam, phi = O.socs_kernels(spec, 0.0, K=8)
+    bank = L.Bank.load(128, lam[None], phi[None])
+    masks = np.stack([W.manhattan_mask(128, s) for s in (3, 4)])
+    img = L.image(bank, dev(masks)).cpu().numpy()
+    for i in range(2):
+        assert rel_l2(img[i, 0], O.image(masks[i], lam, phi)) < TOL
+
+
+@pytest.mark.parametrize("n", [64, 256, 512])
+def test_through_focus_dipole_parity(L, n):
+    # three focus planes, dipole source, curvilinear grey masks, ragged batch of 3
+    spec = W.fd_clip_optics(n)
+    bank = L.Bank.from_spec(spec)
+    masks = np.stack([W.curvilinear_mask(n, 100 + s) for s in range(3)])
+    m32 = W.as_f32_exact(masks)
+    img = L.image(bank, dev(m32)).cpu().numpy()
+    for p, F in enumerate(spec.focus_nm):
+        lam, phi = O.socs_kernels(spec, F, K=spec.K)
+        for i in range(3):
+            assert rel_l2(img[i, p], O.image(m32[i], lam, phi)) < TOL, (p, i)
+
+
+def test_k_use_subset_and_empty_batch(L):
+    spec = W.CONFIG1
+    bank = L.Bank.from_spec(spec)
+    m = W.manhattan_mask(128, 9)
+    img = L.image(bank, dev(m[None]), K_use=5).cpu().numpy()
+    lam, phi = O.socs_kernels(spec, 0.0, K=5)
+    assert rel_l2(img[0, 0], O.image(m, lam, phi)) < TOL
+    import torch
+    empty = torch.empty((0, 128, 128), device="cuda")
+    out = L.image(bank, empty)
+    assert out.shape == (0, 1, 128, 128)
+    with pytest.raises(L.LithoError):
+        L.image(bank, dev(m[None]), K_use=9)
+
+
+def test_clear_and_dark_field(L):
+    spec = W.CONFIG1
+    bank = L.Bank.from_spec(spec)
+    lam = bank.eigenvalues()[0]
+    b = bank.b
+    clear = sum(lam[k] * abs(bank.phi(0, k)[b, b]) ** 2 for k in range(bank.K))
+    img = L.image(bank, dev(np.stack([np.ones((128, 128)), np.zeros((128, 128))]))).cpu().numpy()
+    assert np.abs(img[0, 0] - clear).max() < 1e-5 * clear
+    assert np.abs(img[1, 0]).max() == 0.0
+
+
+def test_bench_launch_config_sampled_pixels(L):
+    # 1024 x 1024, K = 24, batch of 16 curvilinear clips: the bench workload
+    spec = W.CONFIG2
+    bank = L.Bank.from_spec(spec)
+    masks = np.stack([W.as_f32_exact(W.curvilinear_mask(1024, 1000 + s)) for s in range(16)])
+    img = L.image(bank, dev(masks)).cpu().numpy()
+    assert np.isfinite(img).all() and img.min() >= 0
+    lam, phi = O.socs_kernels(spec, 0.0, K=24)
+    b = bank.b
+    rng = np.random.default_rng(7)
+    for i in (0, 7, 15):
+        mh = O.mask_spectrum(masks[i], b, "fft")
+        ys = rng.integers(0, 1024, 40)
+        xs = rng.integers(0, 1024, 40)
+        ref = O.image_at(mh, lam, phi, 1024, ys, xs)
+        got = img[i, 0][ys, xs]
+        assert rel_l2(got, ref) < TOL, i
+
+
+def test_large_grid_sampled_pixels(L):
+    # 2048 x 2048 through focus (3 planes, K = 24): sampled pixels per plane
+    spec = W.CONFIG3
+    bank = L.Bank.from_spec(spec)
+    m = W.as_f32_exact(W.curvilinear_mask(2048, 2000))
+    img = L.image(bank, dev(m[None])).cpu().numpy()[0]
+    b = bank.b
+    mh = O.mask_spectrum(m, b, "fft")
+    rng = np.random.default_rng(11)
+    ys = rng.integers(0, 2048, 24)
+    xs = rng.integers(0, 2048, 24)
+    for p, F in enumerate(spec.focus_nm):
+        lam, phi = O.socs_kernels(spec, F, K=24)
+        ref = O.image_at(mh, lam, phi, 2048, ys, xs)
+        assert rel_l2(img[p][ys, xs], ref) < TOL, p
