@@ -1,0 +1,190 @@
+"""Throughput of the SOCS aerial image + ILT adjoint on one MI355X.
+
+One step = one pass of the whole hot path over a batch of synthetic clips:
+mask spectrum, per-kernel column/row transforms, |E_k|^2 accumulation,
+sigmoid resist, L2 loss against a target, and the adjoint (mask gradient).
+The batch is 16 curvilinear 1024 x 1024 clips at 2 nm (NA 0.55, x-dipole
+0.3-0.9, K = 24 SOCS kernels, FP32), resident in HBM before timing starts.
+
+Prints one JSON line (rank 0).  The metric counts clips x planes x N^2 x K
+pixel-kernels per second; forward and adjoint work is counted once.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "aerial-image Mpixel·kernel/s (fwd+adjoint) vs plain FP32; p50/p99 clip latency"
+UNIT = "Mpixel·kernel/s"
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-clips", type=int, default=3, help="clips in the oracle sample")
+    return ap.parse_args()
+
+
+def kernel_model(name, n, Q, B, K, P, clips):
+    """Algorithmic (bytes, flops) of one launch of a pass."""
+    import math
+    lg = math.log2(Q)
+    fft = 5.0 * Q * lg                      # nominal complex FFT flops, length Q
+    if name == "pass_x_fwd":
+        # reads K band rows of Y per row (B complex), writes image + G, reads target
+        by = clips * P * (K * Q * B * 8 + 3 * n * n * 4)
+        fl = clips * P * K * Q * (fft + 3 * Q)
+    elif name == "pass_x_adj":
+        # reads and rewrites K band rows per row, reads G
+        by = clips * P * (2 * K * Q * B * 8 + n * n * 4)
+        fl = clips * P * K * Q * (2 * fft + 2 * Q)
+    elif name == "pass_y_fwd":
+        by = clips * P * K * (2 * B * B * 8 + Q * B * 8)
+        fl = clips * P * K * B * (fft + 6 * B)
+    elif name == "pass_y_adj":
+        by = clips * P * K * (Q * B * 8 + B * B * 8)
+        fl = clips * P * K * B * (fft + 8 * B)
+    else:
+        return None
+    return by, fl
+
+
+def cpu_baseline(n_clips: int):
+    """Oracle (FP64, direct DFT) on the first n_clips clips of the workload."""
+    import numpy as np
+    import oracle as O
+    import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = os.cpu_count()
+    spec = W.CONFIG2
+    banks = [O.socs_kernels(spec, 0.0, K=spec.K)]
+    dt = 0.0
+    for i in range(n_clips):
+        m = W.as_f32_exact(W.curvilinear_mask(spec.n, 1000 + i))
+        T = W.manhattan_target(spec.n, 1100 + i)
+        t0 = time.perf_counter()
+        O.gradient(m, T, banks, 50.0, 0.3, method="direct")
+        dt += time.perf_counter() - t0
+    pk = n_clips * spec.n * spec.n * spec.K
+    return {"value": pk / dt / 1e6, "unit": UNIT, "cores": int(blas_threads), "kind": "oracle",
+            "sample": f"{n_clips} of the 16 clips ({spec.n}x{spec.n}, K={spec.K}), forward+adjoint, "
+                      f"FP64 direct-DFT oracle, {dt:.1f} s (host has {os.cpu_count()} CPUs)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2602_15036_amd import litho as L
+
+    torch.cuda.set_device(0)
+    spec = W.CONFIG2
+    batch = args.batch
+    bank = L.Bank.from_spec(spec)
+    masks = np.stack([W.as_f32_exact(W.curvilinear_mask(spec.n, 1000 + i)) for i in range(batch)])
+    targets = np.stack([W.manhattan_target(spec.n, 1100 + i) for i in range(batch)])
+    d_mask = torch.from_numpy(masks.astype(np.float32)).cuda()
+    d_target = torch.from_numpy(targets.astype(np.float32)).cuda()
+    n, K, P = spec.n, spec.K, len(spec.focus_nm)
+    img = torch.empty((batch, P, n, n), device="cuda")
+    grad = torch.empty((batch, n, n), device="cuda")
+    loss = torch.empty((batch,), device="cuda", dtype=torch.float64)
+
+    def step():
+        L._check(L._lib.litho_image_grad(
+            bank.handle, L._dev_ptr(d_mask, "mask"), batch, K, L._dev_ptr(d_target, "target"),
+            L.C.byref(L.A.Resist(slope=50.0, threshold=0.3)), None, L._dev_ptr(img, "image"),
+            L._dev_ptr(loss, "loss", torch.float64), L._dev_ptr(grad, "grad"), L.A.LITHO_PREC_FP32,
+            L.C.c_void_p(L._stream_handle())), "litho_image_grad")
+
+    def fwd():
+        L.image(bank, d_mask, out=img)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    L.profile_read()
+    L.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    L.profile_enable(False)
+    prof = L.profile_read()
+
+    # forward-only throughput (same batch), for reference
+    for _ in range(2):
+        fwd()
+    torch.cuda.synchronize()
+    tf0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd()
+    torch.cuda.synchronize()
+    dtf = time.perf_counter() - tf0
+
+    pk = batch * P * n * n * K
+    ms = dt / args.steps * 1e3
+    value = pk / (dt / args.steps) / 1e6
+    fwd_value = pk / (dtf / args.steps) / 1e6
+
+    info = bank
+    kern = {}
+    for name, (cnt, tot) in prof.items():
+        avg = tot / max(cnt, 1)
+        rec = {"launches": cnt, "avg_ms": avg, "share": tot / (dt * 1e3)}
+        mod = kernel_model(name, n, info.inner_grid, info.B, K, P, batch)
+        if mod:
+            by, fl = mod
+            rec["GBps"] = by / (avg * 1e-3) / 1e9
+            rec["TFLOPs"] = fl / (avg * 1e-3) / 1e12
+        kern[name] = rec
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    by, fl = kernel_model(dom, n, info.inner_grid, info.B, K, P, batch)
+    avg = kern[dom]["avg_ms"] * 1e-3
+    roof = {"kernel": dom, "bound": "alu", "achieved": fl / avg / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": fl / avg / 1e12 / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "hbm_view": {"achieved_GBps": by / avg / 1e9, "peak_GBps": HBM_PEAK_GBS,
+                         "frac": by / avg / 1e9 / HBM_PEAK_GBS}}
+    print(json.dumps({"kernels": kern}), file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"ILT step (image + sigmoid resist + L2 loss + mask gradient), {batch} curvilinear "
+                               f"clips {n}x{n} at 2 nm, NA 0.55 x-dipole 0.3-0.9, K={K}, 1 focus plane, FP32",
+                   "clips": batch, "n": n, "K": K, "planes": P, "inner_grid": info.inner_grid, "band": info.B},
+        "forward_only": {"value": fwd_value, "unit": UNIT, "ms_per_batch": dtf / args.steps * 1e3},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_clips)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

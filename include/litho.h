@@ -117,6 +117,18 @@ int litho_kernels_load(int n, int B, int K, int n_focus, const double *h_lambda,
 
 int litho_kernels_info(const litho_bank_t *bank, litho_bank_info_t *info);
 
+/* Choose the grid the per-kernel transforms run on.  Each field E_k is
+ * band-limited to |f| <= b, so |E_k|^2 is band-limited to |f| <= 2b and
+ * sampling the per-kernel work on a q x q grid with q >= 4b + 1 is exact; the
+ * image is then carried to the n x n grid by one zero-padded transform per
+ * clip and plane (and the residual back by one low-pass transform).
+ *   q = 0: automatic (the default after build/load): the smallest supported
+ *          side >= 4b + 1 below n, else n.
+ *   q = n: transforms on the full grid.
+ *   other: 2^j, 3*2^j or 5*2^j with 4b + 1 <= q <= n (LITHO_E_INVALID otherwise).
+ * Must not be called while work on this bank is in flight. */
+int litho_kernels_set_inner_grid(litho_bank_t *bank, int q);
+
 /* Copy the eigenvalues, h_lambda_out: [n_focus][K]. */
 int litho_kernels_eigenvalues(const litho_bank_t *bank, double *h_lambda_out);
 

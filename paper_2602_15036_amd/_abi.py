@@ -72,6 +72,7 @@ SIGNATURES = {
     "litho_kernels_load": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.POINTER(VP)]),
     "litho_kernels_info": (C.c_int, [VP, C.POINTER(BankInfo)]),
+    "litho_kernels_set_inner_grid": (C.c_int, [VP, C.c_int]),
     "litho_kernels_eigenvalues": (C.c_int, [VP, C.POINTER(C.c_double)]),
     "litho_kernels_phi": (C.c_int, [VP, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     "litho_kernels_free": (None, [VP]),

@@ -78,16 +78,30 @@ void prof_end(const char *name, hipStream_t s) {
 // ============================================================ geometry helpers
 bool pow2_side(int n) { return n >= 64 && n <= 4096 && (n & (n - 1)) == 0; }
 
+// Smallest supported side >= 4b + 1 below n (exact for |E_k|^2, which is
+// band-limited to |f| <= 2b), else n itself.
+int auto_inner_grid(int n, int b) {
+  static const int sizes[] = {64, 96, 128, 160, 256, 320, 512, 640, 768, 1024, 1280, 1536, 2048, 2560, 3072};
+  for (int q : sizes)
+    if (q >= 4 * b + 1 && q < n) return q;
+  return n;
+}
+
 }  // namespace litho
 
 using namespace litho;
 
 // ============================================================ bank
+namespace litho {
+int make_twiddles(int L, float2 **out);
+int set_inner_grid(litho_bank *bk, int q);
+int auto_inner_grid(int n, int b);
+}  // namespace litho
+
 static int upload_bank(litho_bank *bk) {
   HostBank &h = bk->host;
   bk->Bp = (h.B + kTileCols - 1) / kTileCols * kTileCols;
   bk->nt = bk->Bp / kTileCols;
-  bk->Q = h.n;
   LITHO_HIP_TRY(hipGetDevice(&bk->device));
   const size_t per = size_t(bk->nt) * h.B * kTileCols;
   std::vector<float2> tiles(size_t(h.n_focus) * h.K * per, make_float2(0.f, 0.f));
@@ -109,24 +123,52 @@ static int upload_bank(litho_bank *bk) {
     return LITHO_E_NOMEM;
   }
   LITHO_HIP_TRY(hipMemcpy(bk->d_phi, tiles.data(), bk->phi_bytes, hipMemcpyHostToDevice));
-  // Twiddle table exp(-2 pi i e / L), computed in FP64 and rounded once.
-  auto make_tw = [&](int L, float2 **out) -> int {
-    std::vector<float2> tw(L);
-    for (int e = 0; e < L; ++e) {
-      const double a = -2.0 * M_PI * double(e) / double(L);
-      tw[e] = make_float2(float(std::cos(a)), float(std::sin(a)));
-    }
-    if (hipMalloc(out, L * sizeof(float2)) != hipSuccess) {
-      set_error("litho: cannot allocate the twiddle table");
-      return LITHO_E_NOMEM;
-    }
-    LITHO_HIP_TRY(hipMemcpy(*out, tw.data(), L * sizeof(float2), hipMemcpyHostToDevice));
-    return LITHO_OK;
-  };
-  LITHO_TRY(make_tw(h.n, &bk->d_twN));
-  bk->d_twQ = bk->d_twN;
+  LITHO_TRY(make_twiddles(h.n, &bk->d_twN));
+  return set_inner_grid(bk, 0);
+}
+
+namespace litho {
+
+// Twiddle table exp(-2 pi i e / L), computed in FP64 and rounded once.
+int make_twiddles(int L, float2 **out) {
+  std::vector<float2> tw(L);
+  for (int e = 0; e < L; ++e) {
+    const double a = -2.0 * M_PI * double(e) / double(L);
+    tw[e] = make_float2(float(std::cos(a)), float(std::sin(a)));
+  }
+  if (hipMalloc(out, L * sizeof(float2)) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    set_error("litho: cannot allocate the twiddle table");
+    return LITHO_E_NOMEM;
+  }
+  LITHO_HIP_TRY(hipMemcpy(*out, tw.data(), L * sizeof(float2), hipMemcpyHostToDevice));
   return LITHO_OK;
 }
+
+int set_inner_grid(litho_bank *bk, int q) {
+  const HostBank &h = bk->host;
+  if (q == 0) q = auto_inner_grid(h.n, h.b);
+  if (q != h.n && (pass_threads(q) == 0 || q < 4 * h.b + 1 || q > h.n)) {
+    set_error("inner grid %d is not supported for n=%d, b=%d (needs 4b+1 <= q <= n from the FFT plan list)", q,
+              h.n, h.b);
+    return LITHO_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(bk->mu);
+  if (bk->d_twQ && bk->d_twQ != bk->d_twN) {
+    LITHO_HIP_TRY(hipDeviceSynchronize());
+    (void)hipFree(bk->d_twQ);
+  }
+  bk->d_twQ = nullptr;
+  bk->Q = q;
+  if (q == h.n) {
+    bk->d_twQ = bk->d_twN;
+    return LITHO_OK;
+  }
+  return make_twiddles(q, &bk->d_twQ);
+}
+
+}  // namespace litho
 
 extern "C" int litho_kernels_build(const litho_optics_t *optics, litho_bank_t **out) {
   clear_error();
@@ -233,6 +275,15 @@ extern "C" int litho_kernels_info(const litho_bank_t *bk, litho_bank_info_t *inf
   return LITHO_OK;
 }
 
+extern "C" int litho_kernels_set_inner_grid(litho_bank_t *bk, int q) {
+  clear_error();
+  if (!bk || q < 0) {
+    set_error("litho_kernels_set_inner_grid: invalid argument");
+    return LITHO_E_INVALID;
+  }
+  return set_inner_grid(bk, q);
+}
+
 extern "C" int litho_kernels_eigenvalues(const litho_bank_t *bk, double *h_lambda_out) {
   clear_error();
   if (!bk || !h_lambda_out) {
@@ -286,11 +337,15 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
   const HostBank &h = bk->host;
   PassGeo &g = L.g;
   g.N = h.n; g.Q = bk->Q; g.b = h.b; g.B = h.B; g.Bp = bk->Bp; g.nt = bk->nt;
+  g.D = 4 * h.b + 1;
+  g.Dp = (g.D + kTileCols - 1) / kTileCols * kTileCols;
+  g.ntD = g.Dp / kTileCols;
   g.K = K_use; g.Kbank = h.K; g.P = h.n_focus; g.dose = h.dose;
   g.kper = 4;
   g.KC = (K_use + g.kper - 1) / g.kper;
-  const int T = pass_threads(g.Q);
-  L.nblk = g.Q / (256 / T);
+  const bool resample = g.Q != g.N;
+  // loss partials come from the row pass that applies the resist (N grid)
+  L.nblk = g.N / (256 / pass_threads(g.N));
   const size_t N = g.N, Q = g.Q;
   L.b_S1 = align256(size_t(g.nt) * N * kTileCols * sizeof(float2));
   L.b_Mh = align256(size_t(g.nt) * g.B * kTileCols * sizeof(float2));
@@ -298,7 +353,8 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
   L.b_G = (grad && fused) ? align256(N * N * sizeof(float)) : 0;
   L.b_part = grad ? align256(size_t(g.P) * g.KC * g.nt * g.B * kTileCols * sizeof(double2)) : 0;
   L.b_loss = (grad && fused) ? align256(size_t(g.P) * L.nblk * sizeof(double)) : 0;
-  const size_t per = L.b_S1 + L.b_Mh + L.b_Y + L.b_G + L.b_part + L.b_loss;
+  L.b_X = resample ? align256(std::max(N, Q) * g.Dp * sizeof(float2)) : 0;
+  const size_t per = L.b_S1 + L.b_Mh + L.b_Y + L.b_G + L.b_part + L.b_loss + 2 * L.b_X;
   L.per_clip = per;
   const size_t lim = workspace_limit_bytes();
   L.chunk = int(std::max<size_t>(1, std::min<size_t>(size_t(batch), lim / per)));
@@ -340,23 +396,53 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
   auto *Y = reinterpret_cast<float2 *>(p); p += L.b_Y * n;
   auto *G = reinterpret_cast<float *>(p); p += L.b_G * n;
   auto *part = reinterpret_cast<double2 *>(p); p += L.b_part * n;
-  auto *lossp = reinterpret_cast<double *>(p);
+  auto *lossp = reinterpret_cast<double *>(p); p += L.b_loss * n;
+  auto *X1 = reinterpret_cast<float2 *>(p); p += L.b_X * n;
+  auto *X2 = reinterpret_cast<float2 *>(p);
   const bool fused = target != nullptr;
+  const bool resample = g.Q != g.N;
   const size_t NN = size_t(g.N) * g.N;
-  // Per-clip strides inside the chunk follow the per-clip block sizes.
-  LITHO_TRY(run_mask_spectrum(mask, S1, Mh, g, bk->d_twN, n, s));
+  const int h2 = 2 * g.b;
+  const float2 *twN = bk->d_twN, *twQ = bk->d_twQ;
+  // mask spectrum (once per clip, shared by every plane)
+  LITHO_TRY(run_rows_fwd_real("mask_rows", g.N, mask, NN, S1, g.b, g.Bp, twN,
+                              float(1.0 / (double(g.N) * double(g.N))), n, s));
+  LITHO_TRY(run_col_fft("mask_cols", g.N, -1, S1, Mh, g.nt, -1, g.b, twN, 1.0f, n, s));
+  EpiPtrs ep;
+  ep.image = image;
+  ep.target = grad && fused ? target : nullptr;
+  ep.G = G;
+  ep.loss_part = lossp;
   for (int pl = 0; pl < g.P; ++pl) {
     g.p = pl;
-    LITHO_TRY(run_pass_y_fwd(bk->d_phi, Mh, Y, g, bk->d_twQ, n, s));
-    LITHO_TRY(run_pass_x_fwd(Y, image, grad && fused ? target : nullptr, G, lossp, g, bk->d_twQ, n, s));
+    LITHO_TRY(run_pass_y_fwd(bk->d_phi, Mh, Y, g, twQ, n, s));
+    if (!resample) {
+      LITHO_TRY(run_pass_x_fwd(Y, ep, nullptr, g, twQ, n, s));
+    } else {
+      LITHO_TRY(run_pass_x_fwd(Y, EpiPtrs{}, X1, g, twQ, n, s));
+      LITHO_TRY(run_col_fft("up_cols_q", g.Q, -1, X1, X2, g.ntD, -1, h2, twQ, 1.0f, n, s));
+      LITHO_TRY(run_col_fft("up_cols_n", g.N, +1, X2, X1, g.ntD, h2, -1, twN, 1.0f, n, s));
+      if (ep.image || ep.target)
+        LITHO_TRY(run_rows_inv_real("up_rows", g.N, X1, h2, g.Dp, nullptr, ep, g, twN, 1.0f, n, s));
+    }
     if (!grad) continue;
     const float *Gp = fused ? G : grad_image + size_t(pl) * NN;
     const size_t gstride = fused ? NN : size_t(g.P) * NN;
-    LITHO_TRY(run_pass_x_adj(Y, Gp, gstride, g, bk->d_twQ, n, s));
-    LITHO_TRY(run_pass_y_adj(Y, bk->d_phi, part, g, bk->d_twQ, n, s));
+    if (!resample) {
+      LITHO_TRY(run_pass_x_adj(Y, Gp, gstride, nullptr, g, twQ, n, s));
+    } else {
+      // G low-passed to |f| <= 2b and sampled on the Q grid (scaled by 1/Q^2)
+      LITHO_TRY(run_rows_fwd_real("down_rows", g.N, Gp, gstride, X1, h2, g.Dp, twN, 1.0f, n, s));
+      LITHO_TRY(run_col_fft("down_cols_n", g.N, -1, X1, X2, g.ntD, -1, h2, twN, 1.0f, n, s));
+      LITHO_TRY(run_col_fft("down_cols_q", g.Q, +1, X2, X1, g.ntD, h2, -1, twQ,
+                            float(1.0 / (double(g.Q) * double(g.Q))), n, s));
+      LITHO_TRY(run_pass_x_adj(Y, nullptr, 0, X1, g, twQ, n, s));
+    }
+    LITHO_TRY(run_pass_y_adj(Y, bk->d_phi, part, g, twQ, n, s));
   }
   if (grad) {
-    LITHO_TRY(run_grad_finish(part, g.P * g.KC, S1, grad_mask, g, bk->d_twN, n, s));
+    LITHO_TRY(run_grad_cols(part, g.P * g.KC, S1, g, twN, n, s));
+    LITHO_TRY(run_rows_inv_real("grad_rows", g.N, S1, g.b, g.Bp, grad_mask, EpiPtrs{}, g, twN, 2.0f, n, s));
     if (fused && loss) LITHO_TRY(run_loss_reduce(lossp, g.P * L.nblk, loss, n, s));
   }
   return LITHO_OK;

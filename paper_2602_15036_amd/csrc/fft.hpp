@@ -251,6 +251,15 @@ template <> struct FftPlan<512> { static constexpr int T = 32; using R = Radices
 template <> struct FftPlan<1024> { static constexpr int T = 64; using R = Radices<16, 16, 4>; };
 template <> struct FftPlan<2048> { static constexpr int T = 64; using R = Radices<16, 16, 8>; };
 template <> struct FftPlan<4096> { static constexpr int T = 128; using R = Radices<16, 16, 16>; };
+template <> struct FftPlan<96> { static constexpr int T = 8; using R = Radices<12, 4, 2>; };
+template <> struct FftPlan<160> { static constexpr int T = 8; using R = Radices<10, 4, 4>; };
+template <> struct FftPlan<320> { static constexpr int T = 16; using R = Radices<20, 4, 4>; };
+template <> struct FftPlan<640> { static constexpr int T = 32; using R = Radices<10, 4, 4, 4>; };
+template <> struct FftPlan<768> { static constexpr int T = 32; using R = Radices<12, 8, 8>; };
+template <> struct FftPlan<1280> { static constexpr int T = 64; using R = Radices<20, 4, 4, 4>; };
+template <> struct FftPlan<1536> { static constexpr int T = 64; using R = Radices<12, 8, 8, 2>; };
+template <> struct FftPlan<2560> { static constexpr int T = 64; using R = Radices<10, 8, 8, 4>; };
+template <> struct FftPlan<3072> { static constexpr int T = 64; using R = Radices<16, 16, 12>; };
 
 // LDS index with one pad slot every 16 complex values (breaks the power-of-two
 // strides of the Stockham scatter).

@@ -3,24 +3,35 @@
 // Data layout.  Every band-limited intermediate is "tile-major": columns are
 // grouped in tiles of kC = 4 adjacent frequency columns, and a tile stores all
 // its rows contiguously, [tile][row][kC].  A column pass then reads and writes
-// one contiguous block per tile, and a row pass handling kRowsPerChunk rows
-// moves kC * rows * 8 bytes contiguous per tile.
+// one contiguous block per tile, and a row pass handling RPB rows moves
+// RPB * kC * 8 bytes contiguous per tile.
+//
+// Grids.  The mask and the outputs live on the N x N grid.  The coherent
+// fields E_k are band-limited to |f| <= b, so |E_k|^2 is band-limited to
+// |f| <= 2b: sampling the per-kernel work on a Q x Q grid with Q >= 4b + 1 is
+// exact, and the image is carried to the N grid by one zero-padded transform
+// per clip.  Q == N skips that step.
 //
 // Forward per clip (Eq. 4, thin mask):
-//   mask_rows   : real rows -> row DFT, keep |kx| <= b, scale 1/N^2   -> S1 [N x Bp]
-//   col_fft     : column DFT of S1, keep |ky| <= b                   -> Mh [B x Bp]
-// per focus plane and kernel k:
-//   pass_y_fwd  : X = Phi'_k * Mh, inverse column DFT (B -> Q rows)  -> Y_k [Q x Bp]
-//   pass_x_fwd  : per row, loop k: inverse row DFT of Y_k, |.|^2 accumulate;
-//                 epilogue: image, sigmoid resist, loss partial, residual G.
+//   rows_fwd_real : real rows -> row DFT, keep |kx| <= b, scale 1/N^2    -> S1 [N x Bp]
+//   col_fft       : column DFT of S1, keep |ky| <= b                     -> Mh [B x Bp]
+// per focus plane:
+//   pass_y_fwd    : per kernel k: X = Phi'_k * Mh, inverse column DFT (B -> Q rows) -> Y_k
+//   pass_x_fwd    : per row, loop k: inverse row DFT of Y_k, |.|^2 accumulate; then
+//                   Q == N: image + sigmoid resist + loss partial + residual G;
+//                   Q <  N: forward row DFT of the Q-grid image, keep |gx| <= 2b
+//   (Q < N)  col_fft<Q, -1> keep |gy| <= 2b, col_fft<N, +1> -> rows_inv_real<N>
+//            with the image / resist epilogue
 // Adjoint per focus plane:
-//   pass_x_adj  : per row, loop k: E_k = inverse row DFT of Y_k (recomputed),
-//                 U = G * E_k, forward row DFT, keep |kx| <= b  -> V_k (in place)
-//   pass_y_adj  : per column tile, loop k: forward column DFT of V_k, keep
-//                 |ky| <= b, acc += conj(Phi'_k) * (.) in FP64     -> partials
+//   (Q < N)  rows_fwd_real<N> of G keep |gx| <= 2b, col_fft<N, -1> keep |gy| <= 2b,
+//            col_fft<Q, +1> -> G on the Q grid as a band
+//   pass_x_adj    : per row: G row; loop k: E_k = inverse row DFT of Y_k
+//                   (recomputed), U = G E_k, forward row DFT, keep |kx| <= b -> V_k
+//   pass_y_adj    : per column tile, loop k: forward column DFT of V_k, keep |ky| <= b,
+//                   acc += conj(Phi'_k) (.) in FP64 -> partials
 // Finish per clip:
-//   grad_cols   : sum partials (FP64, fixed order), inverse column DFT -> [N x Bp]
-//   row_inv_real: inverse row DFT, 2 Re(.) -> dL/dm
+//   grad_cols     : sum partials (FP64, fixed order), inverse column DFT -> [N x Bp]
+//   rows_inv_real : inverse row DFT, 2 Re(.) -> dL/dm
 //
 // Phi'_k = sqrt(lambda_k) Phi_k, so I = sum_k |E'_k|^2 and the adjoint
 // accumulator sum_k conj(Phi'_k) DFT(G E'_k) equals sum_k lambda_k conj(Phi_k) DFT(G E_k).
@@ -36,10 +47,11 @@ constexpr int kC = 4;  // columns per tile
 
 struct Geo {
   int N;      // grid side
-  int Q;      // side of the grid the per-kernel transforms run on (== N here)
+  int Q;      // per-kernel grid side
   int b, B;   // band half-width and side
   int Bp;     // B rounded up to kC
   int nt;     // Bp / kC tiles
+  int D, Dp, ntD;  // intensity band 4b + 1, padded, tiles
   int K;      // kernels used per plane
   int Kbank;  // kernels stored per plane in the bank
   int P;      // planes
@@ -50,6 +62,14 @@ struct Geo {
   float slope, thr;
 };
 
+// Outputs of the image epilogue (image, resist, loss, residual).
+struct Epi {
+  float *image;            // [clip][P][N][N] or nullptr
+  const float *target;     // [clip][N][N] or nullptr (no resist)
+  float *G;                // [clip][N][N] residual dL/dI (when target)
+  double *loss_part;       // [clip][P][nblk]
+};
+
 __device__ __forceinline__ int band_row_of(int pos, int L, int h) {
   // frequency position pos in [0, L) -> centred band row, or -1 if |f| > h
   if (pos <= h) return pos + h;
@@ -57,35 +77,118 @@ __device__ __forceinline__ int band_row_of(int pos, int L, int h) {
   return -1;
 }
 
-// ------------------------------------------------------------ mask rows
-// S1[clip][jt][y][c] = scale * sum_x m[y][x] exp(-2 pi i kx x / N), kx = jt*kC + c - b.
-template <int N>
-__global__ __launch_bounds__(256) void k_mask_rows(const float *__restrict__ mask, cf *__restrict__ S1,
-                                                   Geo g, const cf *__restrict__ tw, float scale) {
-  constexpr int T = FftPlan<N>::T, E = N / T, RPB = 256 / T;
+__device__ __forceinline__ int pos_of_band_row(int r, int h, int L) {
+  return r - h < 0 ? r - h + L : r - h;
+}
+
+// Copies rows y0..y0+RPB of a tiled band array [tiles][L][kC] into stage[RPB][Wp].
+template <int RPB>
+__device__ __forceinline__ void load_band_rows(const cf *__restrict__ src, int L, cf *stage, int Wp, int y0) {
+  const int chunk = RPB * kC;
+  for (int e = threadIdx.x; e < RPB * Wp; e += blockDim.x) {
+    const int jt = e / chunk, r = e % chunk, rr = r / kC, c = r % kC;
+    stage[rr * Wp + jt * kC + c] = src[(size_t(jt) * L + y0 + rr) * kC + c];
+  }
+}
+
+template <int RPB>
+__device__ __forceinline__ void store_band_rows(cf *__restrict__ dst, int L, const cf *stage, int Wp, int y0) {
+  const int chunk = RPB * kC;
+  for (int e = threadIdx.x; e < RPB * Wp; e += blockDim.x) {
+    const int jt = e / chunk, r = e % chunk, rr = r / kC, c = r % kC;
+    dst[(size_t(jt) * L + y0 + rr) * kC + c] = stage[rr * Wp + jt * kC + c];
+  }
+}
+
+// Block-wide FP64 sum in fixed order; `red` holds blockDim.x doubles.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  __syncthreads();
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// Image epilogue at pixel (y, x) of the N grid: image write, sigmoid resist,
+// residual G = 2 (Z - T) a Z (1 - Z); returns (Z - T)^2 (0 without target).
+__device__ __forceinline__ double image_epilogue(const Epi &ep, const Geo &g, int clip, int y, int x, float I) {
+  const size_t NN = size_t(g.N) * g.N;
+  if (ep.image) ep.image[(size_t(clip) * g.P + g.p) * NN + size_t(y) * g.N + x] = I;
+  if (!ep.target) return 0.0;
+  const float z = 1.0f / (1.0f + expf(-g.slope * (I - g.thr)));
+  const float d = z - ep.target[size_t(clip) * NN + size_t(y) * g.N + x];
+  ep.G[size_t(clip) * NN + size_t(y) * g.N + x] = 2.0f * d * g.slope * z * (1.0f - z);
+  return double(d) * double(d);
+}
+
+// ------------------------------------------------------------ real rows -> band
+// out[clip][jt][y][c] = scale * sum_x in[y][x] exp(-2 pi i kx x / L), |kx| <= h,
+// kx = jt*kC + c - h; the Wp - (2h+1) pad columns are written as zeros.
+template <int L>
+__global__ __launch_bounds__(256) void k_rows_fwd_real(const float *__restrict__ in, size_t in_clip,
+                                                       cf *__restrict__ out, int h, int Wp,
+                                                       const cf *__restrict__ tw, float scale) {
+  constexpr int T = FftPlan<L>::T, E = L / T, RPB = 256 / T;
   extern __shared__ cf smem[];
-  cf *stage = smem;                              // [RPB][Bp]
-  cf *xch = smem + RPB * g.Bp;                   // [RPB][lds_len<N>]
+  cf *stage = smem;                      // [RPB][Wp]
+  cf *xch = smem + RPB * Wp;             // [RPB][lds_len<L>]
   const int row = threadIdx.x / T, t = threadIdx.x % T;
   const int y0 = blockIdx.x * RPB, y = y0 + row, clip = blockIdx.y;
-  const float *src = mask + (size_t(clip) * N + y) * N;
+  const float *src = in + clip * in_clip + size_t(y) * L;
   cf v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = cmake(src[t + T * i], 0.0f);
-  fft<N, -1>(v, xch + row * lds_len<N>(), t, tw);
-  cf *st = stage + row * g.Bp;
+  fft<L, -1>(v, xch + row * lds_len<L>(), t, tw);
+  cf *st = stage + row * Wp;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const int j = band_row_of(t + T * i, N, g.b);
+    const int j = band_row_of(t + T * i, L, h);
     if (j >= 0) st[j] = cscale(v[i], scale);
   }
-  for (int j = g.B + t; j < g.Bp; j += T) st[j] = cmake(0.f, 0.f);
+  for (int j = 2 * h + 1 + t; j < Wp; j += T) st[j] = cmake(0.f, 0.f);
   __syncthreads();
-  cf *dst = S1 + size_t(clip) * g.nt * N * kC;
-  const int chunk = RPB * kC;
-  for (int e = threadIdx.x; e < RPB * g.Bp; e += blockDim.x) {
-    const int jt = e / chunk, r = e % chunk, rr = r / kC, c = r % kC;
-    dst[(size_t(jt) * N + y0 + rr) * kC + c] = stage[rr * g.Bp + jt * kC + c];
+  store_band_rows<RPB>(out + size_t(clip) * (Wp / kC) * L * kC, L, stage, Wp, y0);
+}
+
+// ------------------------------------------------------------ band rows -> real rows
+// v = sum_kx in(y, kx) exp(+2 pi i kx x / L); MODE 0: out[y][x] = scale Re v;
+// MODE 1: I = scale Re v through the image / resist epilogue (L == N).
+template <int L, int MODE>
+__global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in, int h, int Wp,
+                                                       float *__restrict__ out, Epi ep, Geo g,
+                                                       const cf *__restrict__ tw, float scale) {
+  constexpr int T = FftPlan<L>::T, E = L / T, RPB = 256 / T;
+  extern __shared__ cf smem[];
+  cf *stage = smem;
+  cf *xch = smem + RPB * Wp;
+  const int row = threadIdx.x / T, t = threadIdx.x % T;
+  const int y0 = blockIdx.x * RPB, y = y0 + row, clip = blockIdx.y;
+  load_band_rows<RPB>(in + size_t(clip) * (Wp / kC) * L * kC, L, stage, Wp, y0);
+  __syncthreads();
+  const cf *st = stage + row * Wp;
+  cf v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int j = band_row_of(t + T * i, L, h);
+    v[i] = j >= 0 ? st[j] : cmake(0.f, 0.f);
+  }
+  __syncthreads();
+  fft<L, +1>(v, xch + row * lds_len<L>(), t, tw);
+  if constexpr (MODE == 0) {
+    float *dst = out + (size_t(clip) * L + y) * L;
+#pragma unroll
+    for (int i = 0; i < E; ++i) dst[t + T * i] = scale * v[i].x;
+  } else {
+    double lsum = 0.0;
+#pragma unroll
+    for (int i = 0; i < E; ++i) lsum += image_epilogue(ep, g, clip, y, t + T * i, scale * v[i].x);
+    if (ep.target) {
+      const double s = block_sum(lsum, reinterpret_cast<double *>(smem));
+      if (threadIdx.x == 0) ep.loss_part[(size_t(clip) * g.P + g.p) * gridDim.x + blockIdx.x] = s;
+    }
   }
 }
 
@@ -114,8 +217,7 @@ __global__ __launch_bounds__(512) void k_col_fft(const cf *__restrict__ in, cf *
   }
   for (int e = threadIdx.x; e < rin * kC; e += blockDim.x) {
     const int r = e / kC, cc = e % kC;
-    int pos = r;
-    if (in_h >= 0) pos = r - in_h < 0 ? r - in_h + L : r - in_h;
+    const int pos = in_h < 0 ? r : pos_of_band_row(r, in_h, L);
     smem[cc * lds_len<L>() + lpad(pos)] = src[e];
   }
   __syncthreads();
@@ -154,8 +256,7 @@ __global__ __launch_bounds__(512) void k_pass_y_fwd(const cf *__restrict__ bank,
   const cf *mh = Mh + (size_t(clip) * g.nt + jt) * g.B * kC;
   for (int e = threadIdx.x; e < g.B * kC; e += blockDim.x) {
     const int r = e / kC, cc = e % kC;
-    const int pos = r - g.b < 0 ? r - g.b + Q : r - g.b;
-    smem[cc * lds_len<Q>() + lpad(pos)] = cmul(ph[e], mh[e]);
+    smem[cc * lds_len<Q>() + lpad(pos_of_band_row(r, g.b, Q))] = cmul(ph[e], mh[e]);
   }
   __syncthreads();
   cf v[E];
@@ -171,38 +272,18 @@ __global__ __launch_bounds__(512) void k_pass_y_fwd(const cf *__restrict__ bank,
     dst[e] = smem[(e % kC) * lds_len<Q>() + lpad(e / kC)];
 }
 
-// Loads rows y0..y0+RPB of one kernel's intermediate (all tiles) into `stage`.
-template <int Q, int RPB>
-__device__ __forceinline__ void load_band_rows(const cf *__restrict__ src, cf *stage, int y0, const Geo &g) {
-  const int chunk = RPB * kC;
-  for (int e = threadIdx.x; e < RPB * g.Bp; e += blockDim.x) {
-    const int jt = e / chunk, r = e % chunk, rr = r / kC, c = r % kC;
-    stage[rr * g.Bp + jt * kC + c] = src[(size_t(jt) * Q + y0 + rr) * kC + c];
-  }
-}
-
-template <int Q, int RPB>
-__device__ __forceinline__ void store_band_rows(cf *__restrict__ dst, const cf *stage, int y0, const Geo &g) {
-  const int chunk = RPB * kC;
-  for (int e = threadIdx.x; e < RPB * g.Bp; e += blockDim.x) {
-    const int jt = e / chunk, r = e % chunk, rr = r / kC, c = r % kC;
-    dst[(size_t(jt) * Q + y0 + rr) * kC + c] = stage[rr * g.Bp + jt * kC + c];
-  }
-}
-
 // ------------------------------------------------------------ forward row pass
-// I(y, x) = dose * sum_k |sum_kx Y_k(y, kx) exp(+2 pi i kx x / Q)|^2 and the
-// resist epilogue.  Outputs: image (optional), residual G and loss partials
-// (when target != nullptr).
-template <int Q>
-__global__ __launch_bounds__(256) void k_pass_x_fwd(const cf *__restrict__ Y, float *__restrict__ image,
-                                                    const float *__restrict__ target, float *__restrict__ G,
-                                                    double *__restrict__ loss_part, Geo g,
+// I_Q(y, x) = dose * sum_k |sum_kx Y_k(y, kx) exp(+2 pi i kx x / Q)|^2.
+// OUT 0 (Q == N): image / resist epilogue.  OUT 1 (Q < N): forward row DFT of
+// the I_Q row, keep |gx| <= 2b, scale 1/Q^2, store tiled [ntD][Q][kC] in Ib.
+template <int Q, int OUT>
+__global__ __launch_bounds__(256) void k_pass_x_fwd(const cf *__restrict__ Y, Epi ep, cf *__restrict__ Ib, Geo g,
                                                     const cf *__restrict__ tw) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
   extern __shared__ cf smem[];
+  const int Wst = OUT == 0 ? g.Bp : max(g.Bp, g.Dp);
   cf *stage = smem;
-  cf *xch = smem + RPB * g.Bp;
+  cf *xch = smem + RPB * Wst;
   const int row = threadIdx.x / T, t = threadIdx.x % T;
   const int y0 = blockIdx.x * RPB, y = y0 + row, clip = blockIdx.y;
   float acc[E];
@@ -210,7 +291,7 @@ __global__ __launch_bounds__(256) void k_pass_x_fwd(const cf *__restrict__ Y, fl
   for (int i = 0; i < E; ++i) acc[i] = 0.f;
   const cf *st = stage + row * g.Bp;
   for (int k = 0; k < g.K; ++k) {
-    load_band_rows<Q, RPB>(Y + (size_t(clip) * g.K + k) * g.nt * size_t(Q) * kC, stage, y0, g);
+    load_band_rows<RPB>(Y + (size_t(clip) * g.K + k) * g.nt * size_t(Q) * kC, Q, stage, g.Bp, y0);
     __syncthreads();
     cf v[E];
 #pragma unroll
@@ -223,54 +304,74 @@ __global__ __launch_bounds__(256) void k_pass_x_fwd(const cf *__restrict__ Y, fl
 #pragma unroll
     for (int i = 0; i < E; ++i) acc[i] += cabs2(v[i]);
   }
-  const size_t pix = (size_t(clip) * g.P + g.p) * size_t(Q) * Q + size_t(y) * Q;
-  double lsum = 0.0;
+  if constexpr (OUT == 0) {
+    double lsum = 0.0;
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int x = t + T * i;
-    const float I = acc[i] * g.dose;
-    if (image) image[pix + x] = I;
-    if (target) {
-      const float z = 1.0f / (1.0f + expf(-g.slope * (I - g.thr)));
-      const float d = z - target[(size_t(clip) * Q + y) * Q + x];
-      G[(size_t(clip) * Q + y) * Q + x] = 2.0f * d * g.slope * z * (1.0f - z);
-      lsum += double(d) * double(d);
+    for (int i = 0; i < E; ++i) lsum += image_epilogue(ep, g, clip, y, t + T * i, acc[i] * g.dose);
+    if (ep.target) {
+      const double s = block_sum(lsum, reinterpret_cast<double *>(smem));
+      if (threadIdx.x == 0) ep.loss_part[(size_t(clip) * g.P + g.p) * gridDim.x + blockIdx.x] = s;
     }
-  }
-  if (target) {
-    // block reduction in FP64, fixed order
-    double *red = reinterpret_cast<double *>(smem);
-    __syncthreads();
-    red[threadIdx.x] = lsum;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
+  } else {
+    cf v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = cmake(acc[i], 0.f);
+    fft<Q, -1>(v, xch + row * lds_len<Q>(), t, tw);
+    const float sc = g.dose / (float(Q) * float(Q));
+    cf *so = stage + row * g.Dp;
+    const int h2 = 2 * g.b;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int j = band_row_of(t + T * i, Q, h2);
+      if (j >= 0) so[j] = cscale(v[i], sc);
     }
-    if (threadIdx.x == 0) loss_part[(size_t(clip) * g.P + g.p) * gridDim.x + blockIdx.x] = red[0];
+    for (int j = g.D + t; j < g.Dp; j += T) so[j] = cmake(0.f, 0.f);
+    __syncthreads();
+    store_band_rows<RPB>(Ib + size_t(clip) * g.ntD * size_t(Q) * kC, Q, stage, g.Dp, y0);
   }
 }
 
 // ------------------------------------------------------------ adjoint row pass
 // V_k(y, kx) = sum_x G(y, x) E'_k(y, x) exp(-2 pi i kx x / Q), |kx| <= b,
 // E'_k recomputed from Y_k; V_k overwrites Y_k.
-template <int Q>
-__global__ __launch_bounds__(256) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Gin,
-                                                    size_t g_clip_stride, Geo g, const cf *__restrict__ tw) {
+// GIN 0: G is a real [Q][Q] array per clip (Q == N), rows strided by Q.
+// GIN 1: G is a band [ntD][Q][kC] (|gx| <= 2b) per clip; its row is synthesised.
+template <int Q, int GIN>
+__global__ __launch_bounds__(256) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Greal,
+                                                    size_t g_clip_stride, const cf *__restrict__ Gband, Geo g,
+                                                    const cf *__restrict__ tw) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
   extern __shared__ cf smem[];
+  const int Wst = GIN == 0 ? g.Bp : max(g.Bp, g.Dp);
   cf *stage = smem;
-  cf *xch = smem + RPB * g.Bp;
+  cf *xch = smem + RPB * Wst;
   const int row = threadIdx.x / T, t = threadIdx.x % T;
   const int y0 = blockIdx.x * RPB, y = y0 + row, clip = blockIdx.y;
   float gr[E];
-  const float *gsrc = Gin + clip * g_clip_stride + size_t(y) * Q;
+  if constexpr (GIN == 0) {
+    const float *gsrc = Greal + clip * g_clip_stride + size_t(y) * Q;
 #pragma unroll
-  for (int i = 0; i < E; ++i) gr[i] = gsrc[t + T * i] * g.dose;
+    for (int i = 0; i < E; ++i) gr[i] = gsrc[t + T * i] * g.dose;
+  } else {
+    load_band_rows<RPB>(Gband + size_t(clip) * g.ntD * size_t(Q) * kC, Q, stage, g.Dp, y0);
+    __syncthreads();
+    const cf *sg = stage + row * g.Dp;
+    const int h2 = 2 * g.b;
+    cf v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int j = band_row_of(t + T * i, Q, h2);
+      v[i] = j >= 0 ? sg[j] : cmake(0.f, 0.f);
+    }
+    __syncthreads();
+    fft<Q, +1>(v, xch + row * lds_len<Q>(), t, tw);
+#pragma unroll
+    for (int i = 0; i < E; ++i) gr[i] = v[i].x * g.dose;
+  }
   cf *st = stage + row * g.Bp;
   for (int k = 0; k < g.K; ++k) {
     cf *yk = Y + (size_t(clip) * g.K + k) * g.nt * size_t(Q) * kC;
-    load_band_rows<Q, RPB>(yk, stage, y0, g);
+    load_band_rows<RPB>(yk, Q, stage, g.Bp, y0);
     __syncthreads();
     cf v[E];
 #pragma unroll
@@ -290,7 +391,7 @@ __global__ __launch_bounds__(256) void k_pass_x_adj(cf *__restrict__ Y, const fl
     }
     for (int j = g.B + t; j < g.Bp; j += T) st[j] = cmake(0.f, 0.f);
     __syncthreads();
-    store_band_rows<Q, RPB>(yk, stage, y0, g);
+    store_band_rows<RPB>(yk, Q, stage, g.Bp, y0);
     __syncthreads();
   }
 }
@@ -373,8 +474,7 @@ __global__ __launch_bounds__(512) void k_grad_cols(const double2 *__restrict__ p
       sy += a.y;
     }
     const int r = e / kC, cc = e % kC;
-    const int pos = r - g.b < 0 ? r - g.b + N : r - g.b;
-    smem[cc * lds_len<N>() + lpad(pos)] = cmake(float(sx * inv), float(sy * inv));
+    smem[cc * lds_len<N>() + lpad(pos_of_band_row(r, g.b, N))] = cmake(float(sx * inv), float(sy * inv));
   }
   __syncthreads();
   cf v[E];
@@ -390,33 +490,6 @@ __global__ __launch_bounds__(512) void k_grad_cols(const double2 *__restrict__ p
     dst[e] = smem[(e % kC) * lds_len<N>() + lpad(e / kC)];
 }
 
-// ------------------------------------------------------------ band rows -> real rows
-// out[clip][y][x] = scale * Re sum_kx in(y, kx) exp(+2 pi i kx x / N)
-template <int N>
-__global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in, float *__restrict__ out,
-                                                       Geo g, const cf *__restrict__ tw, float scale) {
-  constexpr int T = FftPlan<N>::T, E = N / T, RPB = 256 / T;
-  extern __shared__ cf smem[];
-  cf *stage = smem;
-  cf *xch = smem + RPB * g.Bp;
-  const int row = threadIdx.x / T, t = threadIdx.x % T;
-  const int y0 = blockIdx.x * RPB, y = y0 + row, clip = blockIdx.y;
-  load_band_rows<N, RPB>(in + size_t(clip) * g.nt * N * kC, stage, y0, g);
-  __syncthreads();
-  const cf *st = stage + row * g.Bp;
-  cf v[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int j = band_row_of(t + T * i, N, g.b);
-    v[i] = j >= 0 ? st[j] : cmake(0.f, 0.f);
-  }
-  __syncthreads();
-  fft<N, +1>(v, xch + row * lds_len<N>(), t, tw);
-  float *dst = out + (size_t(clip) * N + y) * N;
-#pragma unroll
-  for (int i = 0; i < E; ++i) dst[t + T * i] = scale * v[i].x;
-}
-
 // ------------------------------------------------------------ loss reduction
 __global__ __launch_bounds__(256) void k_loss_reduce(const double *__restrict__ part, int n_per_clip,
                                                      double *__restrict__ loss) {
@@ -424,13 +497,8 @@ __global__ __launch_bounds__(256) void k_loss_reduce(const double *__restrict__ 
   const int clip = blockIdx.x;
   double s = 0.0;
   for (int i = threadIdx.x; i < n_per_clip; i += blockDim.x) s += part[size_t(clip) * n_per_clip + i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) loss[clip] = red[0];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) loss[clip] = s;
 }
 
 }  // namespace dev
@@ -440,17 +508,28 @@ __global__ __launch_bounds__(256) void k_loss_reduce(const double *__restrict__ 
 namespace {
 
 using dev::cf;
+using dev::Epi;
 using dev::FftPlan;
 using dev::Geo;
 using dev::kC;
 using dev::lds_len;
 
-dev::Geo to_geo(const PassGeo &pg) {
+Geo to_geo(const PassGeo &pg) {
   Geo g;
   g.N = pg.N; g.Q = pg.Q; g.b = pg.b; g.B = pg.B; g.Bp = pg.Bp; g.nt = pg.nt;
+  g.D = pg.D; g.Dp = pg.Dp; g.ntD = pg.ntD;
   g.K = pg.K; g.Kbank = pg.Kbank; g.P = pg.P; g.p = pg.p; g.KC = pg.KC; g.kper = pg.kper;
   g.dose = float(pg.dose); g.slope = float(pg.slope); g.thr = float(pg.thr);
   return g;
+}
+
+Epi to_epi(const EpiPtrs &e) {
+  Epi o;
+  o.image = e.image;
+  o.target = e.target;
+  o.G = e.G;
+  o.loss_part = e.loss_part;
+  return o;
 }
 
 template <typename F>
@@ -478,22 +557,43 @@ int launch(const char *name, const void *kernel, dim3 grid, size_t shmem, hipStr
   return LITHO_OK;
 }
 
-template <int N>
-int mask_spectrum_n(const float *mask, cf *S1, cf *Mh, const PassGeo &pg, const cf *twN, int nclips,
-                    hipStream_t s) {
-  constexpr int T = FftPlan<N>::T, RPB = 256 / T;
+#define KPTR(...) reinterpret_cast<const void *>(&__VA_ARGS__)
+
+template <int L>
+int rows_fwd_real_l(const char *name, const float *in, size_t in_clip, cf *out, int h, int Wp, const cf *tw,
+                    float scale, int nclips, hipStream_t s) {
+  constexpr int T = FftPlan<L>::T, RPB = 256 / T;
+  size_t sh = (size_t(RPB) * Wp + size_t(RPB) * lds_len<L>()) * sizeof(cf);
+  return launch(name, KPTR(dev::k_rows_fwd_real<L>), dim3(L / RPB, nclips), sh, s, [&] {
+    hipLaunchKernelGGL(dev::k_rows_fwd_real<L>, dim3(L / RPB, nclips), dim3(256), sh, s, in, in_clip, out, h, Wp,
+                       tw, scale);
+  });
+}
+
+template <int L, int MODE>
+int rows_inv_real_l(const char *name, const cf *in, int h, int Wp, float *out, const EpiPtrs &ep,
+                    const PassGeo &pg, const cf *tw, float scale, int nclips, hipStream_t s) {
+  constexpr int T = FftPlan<L>::T, RPB = 256 / T;
+  size_t sh = (size_t(RPB) * Wp + size_t(RPB) * lds_len<L>()) * sizeof(cf);
+  sh = std::max(sh, size_t(256) * sizeof(double));
   Geo g = to_geo(pg);
-  size_t sh = (size_t(RPB) * g.Bp + size_t(RPB) * lds_len<N>()) * sizeof(cf);
-  LITHO_TRY(launch("mask_rows", reinterpret_cast<const void *>(&dev::k_mask_rows<N>), dim3(N / RPB, nclips), sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_mask_rows<N>, dim3(N / RPB, nclips), dim3(256), sh, s, mask, S1, g, twN,
-                       float(1.0 / (double(N) * double(N))));
-  }));
-  size_t shc = size_t(kC) * lds_len<N>() * sizeof(cf);
-  LITHO_TRY(launch("mask_cols", reinterpret_cast<const void *>(&dev::k_col_fft<N, -1>), dim3(g.nt, nclips), shc, s, [&] {
-    hipLaunchKernelGGL((dev::k_col_fft<N, -1>), dim3(g.nt, nclips), dim3(kC * T), shc, s, S1, Mh, g.nt, -1,
-                       g.b, size_t(g.nt) * N * kC, size_t(g.nt) * g.B * kC, twN, 1.0f);
-  }));
-  return LITHO_OK;
+  Epi e = to_epi(ep);
+  return launch(name, KPTR(dev::k_rows_inv_real<L, MODE>), dim3(L / RPB, nclips), sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_rows_inv_real<L, MODE>), dim3(L / RPB, nclips), dim3(256), sh, s, in, h, Wp, out,
+                       e, g, tw, scale);
+  });
+}
+
+template <int L, int DIR>
+int col_fft_l(const char *name, const cf *in, cf *out, int nt, int in_h, int out_h, const cf *tw, float scale,
+              int nclips, hipStream_t s) {
+  constexpr int T = FftPlan<L>::T;
+  const size_t rin = in_h < 0 ? L : 2 * in_h + 1, rout = out_h < 0 ? L : 2 * out_h + 1;
+  size_t sh = size_t(kC) * lds_len<L>() * sizeof(cf);
+  return launch(name, KPTR(dev::k_col_fft<L, DIR>), dim3(nt, nclips), sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_col_fft<L, DIR>), dim3(nt, nclips), dim3(kC * T), sh, s, in, out, nt, in_h, out_h,
+                       size_t(nt) * rin * kC, size_t(nt) * rout * kC, tw, scale);
+  });
 }
 
 template <int Q>
@@ -502,34 +602,46 @@ int pass_y_fwd_q(const cf *bank, const cf *Mh, cf *Y, const PassGeo &pg, const c
   constexpr int T = FftPlan<Q>::T;
   Geo g = to_geo(pg);
   size_t sh = size_t(kC) * lds_len<Q>() * sizeof(cf);
-  return launch("pass_y_fwd", reinterpret_cast<const void *>(&dev::k_pass_y_fwd<Q>), dim3(g.nt, g.K, nclips), sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_pass_y_fwd<Q>, dim3(g.nt, g.K, nclips), dim3(kC * T), sh, s, bank, Mh, Y, g,
-                       twQ);
+  return launch("pass_y_fwd", KPTR(dev::k_pass_y_fwd<Q>), dim3(g.nt, g.K, nclips), sh, s, [&] {
+    hipLaunchKernelGGL(dev::k_pass_y_fwd<Q>, dim3(g.nt, g.K, nclips), dim3(kC * T), sh, s, bank, Mh, Y, g, twQ);
   });
 }
 
 template <int Q>
-int pass_x_fwd_q(const cf *Y, float *image, const float *target, float *G, double *loss_part,
-                 const PassGeo &pg, const cf *twQ, int nclips, hipStream_t s) {
-  constexpr int T = FftPlan<Q>::T, RPB = 256 / T;
-  Geo g = to_geo(pg);
-  size_t sh = (size_t(RPB) * g.Bp + size_t(RPB) * lds_len<Q>()) * sizeof(cf);
-  sh = std::max(sh, size_t(256) * sizeof(double));
-  return launch("pass_x_fwd", reinterpret_cast<const void *>(&dev::k_pass_x_fwd<Q>), dim3(Q / RPB, nclips), sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_pass_x_fwd<Q>, dim3(Q / RPB, nclips), dim3(256), sh, s, Y, image, target, G,
-                       loss_part, g, twQ);
-  });
-}
-
-template <int Q>
-int pass_x_adj_q(cf *Y, const float *G, size_t g_clip_stride, const PassGeo &pg, const cf *twQ, int nclips,
+int pass_x_fwd_q(const cf *Y, const EpiPtrs &ep, cf *Ib, const PassGeo &pg, const cf *twQ, int nclips,
                  hipStream_t s) {
   constexpr int T = FftPlan<Q>::T, RPB = 256 / T;
   Geo g = to_geo(pg);
-  size_t sh = (size_t(RPB) * g.Bp + size_t(RPB) * lds_len<Q>()) * sizeof(cf);
-  return launch("pass_x_adj", reinterpret_cast<const void *>(&dev::k_pass_x_adj<Q>), dim3(Q / RPB, nclips), sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_pass_x_adj<Q>, dim3(Q / RPB, nclips), dim3(256), sh, s, Y, G, g_clip_stride, g,
-                       twQ);
+  Epi e = to_epi(ep);
+  const bool band = g.Q != g.N;
+  const int Wst = band ? std::max(g.Bp, g.Dp) : g.Bp;
+  size_t sh = (size_t(RPB) * Wst + size_t(RPB) * lds_len<Q>()) * sizeof(cf);
+  sh = std::max(sh, size_t(256) * sizeof(double));
+  if (!band)
+    return launch("pass_x_fwd", KPTR(dev::k_pass_x_fwd<Q, 0>), dim3(Q / RPB, nclips), sh, s, [&] {
+      hipLaunchKernelGGL((dev::k_pass_x_fwd<Q, 0>), dim3(Q / RPB, nclips), dim3(256), sh, s, Y, e, Ib, g, twQ);
+    });
+  return launch("pass_x_fwd", KPTR(dev::k_pass_x_fwd<Q, 1>), dim3(Q / RPB, nclips), sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_pass_x_fwd<Q, 1>), dim3(Q / RPB, nclips), dim3(256), sh, s, Y, e, Ib, g, twQ);
+  });
+}
+
+template <int Q>
+int pass_x_adj_q(cf *Y, const float *G, size_t g_clip_stride, const cf *Gband, const PassGeo &pg, const cf *twQ,
+                 int nclips, hipStream_t s) {
+  constexpr int T = FftPlan<Q>::T, RPB = 256 / T;
+  Geo g = to_geo(pg);
+  const bool band = Gband != nullptr;
+  const int Wst = band ? std::max(g.Bp, g.Dp) : g.Bp;
+  size_t sh = (size_t(RPB) * Wst + size_t(RPB) * lds_len<Q>()) * sizeof(cf);
+  if (!band)
+    return launch("pass_x_adj", KPTR(dev::k_pass_x_adj<Q, 0>), dim3(Q / RPB, nclips), sh, s, [&] {
+      hipLaunchKernelGGL((dev::k_pass_x_adj<Q, 0>), dim3(Q / RPB, nclips), dim3(256), sh, s, Y, G, g_clip_stride,
+                         Gband, g, twQ);
+    });
+  return launch("pass_x_adj", KPTR(dev::k_pass_x_adj<Q, 1>), dim3(Q / RPB, nclips), sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_pass_x_adj<Q, 1>), dim3(Q / RPB, nclips), dim3(256), sh, s, Y, G, g_clip_stride,
+                       Gband, g, twQ);
   });
 }
 
@@ -539,7 +651,7 @@ int pass_y_adj_qu(const cf *V, const cf *bank, double2 *part, const PassGeo &pg,
   constexpr int T = FftPlan<Q>::T;
   Geo g = to_geo(pg);
   size_t sh = size_t(kC) * lds_len<Q>() * sizeof(cf);
-  return launch("pass_y_adj", reinterpret_cast<const void *>(&dev::k_pass_y_adj<Q, U>), dim3(g.nt, g.KC, nclips), sh, s, [&] {
+  return launch("pass_y_adj", KPTR(dev::k_pass_y_adj<Q, U>), dim3(g.nt, g.KC, nclips), sh, s, [&] {
     hipLaunchKernelGGL((dev::k_pass_y_adj<Q, U>), dim3(g.nt, g.KC, nclips), dim3(kC * T), sh, s, V, bank, part,
                        g, twQ);
   });
@@ -561,80 +673,124 @@ int pass_y_adj_q(const cf *V, const cf *bank, double2 *part, const PassGeo &pg, 
 }
 
 template <int N>
-int grad_finish_n(const double2 *part, int nparts, cf *tmp, float *grad, const PassGeo &pg, const cf *twN,
-                  int nclips, hipStream_t s) {
-  constexpr int T = FftPlan<N>::T, RPB = 256 / T;
+int grad_cols_n(const double2 *part, int nparts, cf *tmp, const PassGeo &pg, const cf *twN, int nclips,
+                hipStream_t s) {
+  constexpr int T = FftPlan<N>::T;
   Geo g = to_geo(pg);
   size_t shc = size_t(kC) * lds_len<N>() * sizeof(cf);
-  LITHO_TRY(launch("grad_cols", reinterpret_cast<const void *>(&dev::k_grad_cols<N>), dim3(g.nt, nclips), shc, s, [&] {
-    hipLaunchKernelGGL(dev::k_grad_cols<N>, dim3(g.nt, nclips), dim3(kC * T), shc, s, part, nparts, tmp, g,
-                       twN);
-  }));
-  size_t sh = (size_t(RPB) * g.Bp + size_t(RPB) * lds_len<N>()) * sizeof(cf);
-  return launch("grad_rows", reinterpret_cast<const void *>(&dev::k_rows_inv_real<N>), dim3(N / RPB, nclips), sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_rows_inv_real<N>, dim3(N / RPB, nclips), dim3(256), sh, s, tmp, grad, g, twN,
-                       2.0f);
+  return launch("grad_cols", KPTR(dev::k_grad_cols<N>), dim3(g.nt, nclips), shc, s, [&] {
+    hipLaunchKernelGGL(dev::k_grad_cols<N>, dim3(g.nt, nclips), dim3(kC * T), shc, s, part, nparts, tmp, g, twN);
   });
 }
 
 }  // namespace
 
-#define LITHO_DISPATCH_N(n, CALL)                 \
-  switch (n) {                                    \
-    case 64: { constexpr int NN = 64; return CALL; }     \
-    case 128: { constexpr int NN = 128; return CALL; }   \
-    case 256: { constexpr int NN = 256; return CALL; }   \
-    case 512: { constexpr int NN = 512; return CALL; }   \
-    case 1024: { constexpr int NN = 1024; return CALL; } \
-    case 2048: { constexpr int NN = 2048; return CALL; } \
-    case 4096: { constexpr int NN = 4096; return CALL; } \
-    default:                                      \
-      set_error("unsupported transform length %d", n); \
-      return LITHO_E_UNSUPPORTED;                 \
+#define LITHO_CASE(L, CALL) \
+  case L: {                 \
+    constexpr int NN = L;   \
+    return CALL;            \
   }
 
-int run_mask_spectrum(const float *mask, cf2 *S1, cf2 *Mh, const PassGeo &pg, const cf2 *twN, int nclips,
-                      hipStream_t s) {
-  LITHO_DISPATCH_N(pg.N, (mask_spectrum_n<NN>(mask, (cf *)S1, (cf *)Mh, pg, (const cf *)twN, nclips, s)));
+// Grid sides (masks, outputs): powers of two.
+#define LITHO_DISPATCH_N(n, CALL)                        \
+  switch (n) {                                           \
+    LITHO_CASE(64, CALL)                                 \
+    LITHO_CASE(128, CALL)                                \
+    LITHO_CASE(256, CALL)                                \
+    LITHO_CASE(512, CALL)                                \
+    LITHO_CASE(1024, CALL)                               \
+    LITHO_CASE(2048, CALL)                               \
+    LITHO_CASE(4096, CALL)                               \
+    default:                                             \
+      set_error("unsupported grid side %d", n);          \
+      return LITHO_E_UNSUPPORTED;                        \
+  }
+
+// Per-kernel grid sides: powers of two and 3 or 5 times a power of two.
+#define LITHO_DISPATCH_Q(q, CALL)                        \
+  switch (q) {                                           \
+    LITHO_CASE(64, CALL)                                 \
+    LITHO_CASE(96, CALL)                                 \
+    LITHO_CASE(128, CALL)                                \
+    LITHO_CASE(160, CALL)                                \
+    LITHO_CASE(256, CALL)                                \
+    LITHO_CASE(320, CALL)                                \
+    LITHO_CASE(512, CALL)                                \
+    LITHO_CASE(640, CALL)                                \
+    LITHO_CASE(768, CALL)                                \
+    LITHO_CASE(1024, CALL)                               \
+    LITHO_CASE(1280, CALL)                               \
+    LITHO_CASE(1536, CALL)                               \
+    LITHO_CASE(2048, CALL)                               \
+    LITHO_CASE(2560, CALL)                               \
+    LITHO_CASE(3072, CALL)                               \
+    LITHO_CASE(4096, CALL)                               \
+    default:                                             \
+      set_error("unsupported inner grid side %d", q);    \
+      return LITHO_E_UNSUPPORTED;                        \
+  }
+
+int run_rows_fwd_real(const char *name, int L, const float *in, size_t in_clip, cf2 *out, int h, int Wp,
+                      const cf2 *tw, float scale, int nclips, hipStream_t s) {
+  LITHO_DISPATCH_N(L, (rows_fwd_real_l<NN>(name, in, in_clip, (cf *)out, h, Wp, (const cf *)tw, scale, nclips,
+                                           s)));
+}
+int run_rows_inv_real(const char *name, int L, const cf2 *in, int h, int Wp, float *out, const EpiPtrs &ep,
+                      const PassGeo &g, const cf2 *tw, float scale, int nclips, hipStream_t s) {
+  if (ep.image || ep.target) {
+    LITHO_DISPATCH_N(L, (rows_inv_real_l<NN, 1>(name, (const cf *)in, h, Wp, out, ep, g, (const cf *)tw, scale,
+                                                 nclips, s)));
+  }
+  LITHO_DISPATCH_N(L, (rows_inv_real_l<NN, 0>(name, (const cf *)in, h, Wp, out, ep, g, (const cf *)tw, scale,
+                                               nclips, s)));
+}
+int run_col_fft(const char *name, int L, int dir, const cf2 *in, cf2 *out, int nt, int in_h, int out_h,
+                const cf2 *tw, float scale, int nclips, hipStream_t s) {
+  if (dir < 0) {
+    LITHO_DISPATCH_Q(L, (col_fft_l<NN, -1>(name, (const cf *)in, (cf *)out, nt, in_h, out_h, (const cf *)tw,
+                                            scale, nclips, s)));
+  }
+  LITHO_DISPATCH_Q(L, (col_fft_l<NN, +1>(name, (const cf *)in, (cf *)out, nt, in_h, out_h, (const cf *)tw, scale,
+                                          nclips, s)));
 }
 int run_pass_y_fwd(const cf2 *bank, const cf2 *Mh, cf2 *Y, const PassGeo &pg, const cf2 *twQ, int nclips,
                    hipStream_t s) {
-  LITHO_DISPATCH_N(pg.Q, (pass_y_fwd_q<NN>((const cf *)bank, (const cf *)Mh, (cf *)Y, pg, (const cf *)twQ,
+  LITHO_DISPATCH_Q(pg.Q, (pass_y_fwd_q<NN>((const cf *)bank, (const cf *)Mh, (cf *)Y, pg, (const cf *)twQ,
                                            nclips, s)));
 }
-int run_pass_x_fwd(const cf2 *Y, float *image, const float *target, float *G, double *loss_part,
-                   const PassGeo &pg, const cf2 *twQ, int nclips, hipStream_t s) {
-  LITHO_DISPATCH_N(pg.Q, (pass_x_fwd_q<NN>((const cf *)Y, image, target, G, loss_part, pg, (const cf *)twQ,
-                                           nclips, s)));
-}
-int run_pass_x_adj(cf2 *Y, const float *G, size_t g_clip_stride, const PassGeo &pg, const cf2 *twQ, int nclips,
+int run_pass_x_fwd(const cf2 *Y, const EpiPtrs &ep, cf2 *Ib, const PassGeo &pg, const cf2 *twQ, int nclips,
                    hipStream_t s) {
-  LITHO_DISPATCH_N(pg.Q, (pass_x_adj_q<NN>((cf *)Y, G, g_clip_stride, pg, (const cf *)twQ, nclips, s)));
+  LITHO_DISPATCH_Q(pg.Q, (pass_x_fwd_q<NN>((const cf *)Y, ep, (cf *)Ib, pg, (const cf *)twQ, nclips, s)));
+}
+int run_pass_x_adj(cf2 *Y, const float *G, size_t g_clip_stride, const cf2 *Gband, const PassGeo &pg,
+                   const cf2 *twQ, int nclips, hipStream_t s) {
+  LITHO_DISPATCH_Q(pg.Q, (pass_x_adj_q<NN>((cf *)Y, G, g_clip_stride, (const cf *)Gband, pg, (const cf *)twQ,
+                                           nclips, s)));
 }
 int run_pass_y_adj(const cf2 *V, const cf2 *bank, double2 *part, const PassGeo &pg, const cf2 *twQ, int nclips,
                    hipStream_t s) {
-  LITHO_DISPATCH_N(pg.Q, (pass_y_adj_q<NN>((const cf *)V, (const cf *)bank, part, pg, (const cf *)twQ, nclips,
+  LITHO_DISPATCH_Q(pg.Q, (pass_y_adj_q<NN>((const cf *)V, (const cf *)bank, part, pg, (const cf *)twQ, nclips,
                                            s)));
 }
-int run_grad_finish(const double2 *part, int nparts, cf2 *tmp, float *grad, const PassGeo &pg, const cf2 *twN,
-                    int nclips, hipStream_t s) {
-  LITHO_DISPATCH_N(pg.N, (grad_finish_n<NN>(part, nparts, (cf *)tmp, grad, pg, (const cf *)twN, nclips, s)));
+int run_grad_cols(const double2 *part, int nparts, cf2 *tmp, const PassGeo &pg, const cf2 *twN, int nclips,
+                  hipStream_t s) {
+  LITHO_DISPATCH_N(pg.N, (grad_cols_n<NN>(part, nparts, (cf *)tmp, pg, (const cf *)twN, nclips, s)));
 }
 int run_loss_reduce(const double *part, int n_per_clip, double *loss, int nclips, hipStream_t s) {
-  return launch("loss_reduce", reinterpret_cast<const void *>(&dev::k_loss_reduce), dim3(nclips), 0, s, [&] {
+  return launch("loss_reduce", KPTR(dev::k_loss_reduce), dim3(nclips), 0, s, [&] {
     hipLaunchKernelGGL(dev::k_loss_reduce, dim3(nclips), dim3(256), 0, s, part, n_per_clip, loss);
   });
 }
 
 int pass_threads(int L) {
   switch (L) {
-    case 64: return FftPlan<64>::T;
-    case 128: return FftPlan<128>::T;
-    case 256: return FftPlan<256>::T;
-    case 512: return FftPlan<512>::T;
-    case 1024: return FftPlan<1024>::T;
-    case 2048: return FftPlan<2048>::T;
-    case 4096: return FftPlan<4096>::T;
+#define LITHO_T(X) \
+  case X:          \
+    return FftPlan<X>::T;
+    LITHO_T(64) LITHO_T(96) LITHO_T(128) LITHO_T(160) LITHO_T(256) LITHO_T(320) LITHO_T(512) LITHO_T(640)
+    LITHO_T(768) LITHO_T(1024) LITHO_T(1280) LITHO_T(1536) LITHO_T(2048) LITHO_T(2560) LITHO_T(3072)
+    LITHO_T(4096)
+#undef LITHO_T
     default: return 0;
   }
 }

@@ -14,13 +14,22 @@ using cf2 = float2;
 // Geometry of one launch sequence (one focus plane of one chunk of clips).
 struct PassGeo {
   int N = 0;      // grid side
-  int Q = 0;      // side of the per-kernel transform grid
-  int b = 0, B = 0, Bp = 0, nt = 0;
+  int Q = 0;      // side of the per-kernel transform grid (Q >= 4b + 1, or Q == N)
+  int b = 0, B = 0, Bp = 0, nt = 0;   // field band |f| <= b, side, padded side, tiles
+  int D = 0, Dp = 0, ntD = 0;         // intensity band |f| <= 2b: side 4b + 1, padded, tiles
   int K = 0;      // kernels used per plane
   int Kbank = 0;  // kernels stored per plane
   int P = 1, p = 0;
   int KC = 1, kper = 1;  // k-chunks of the adjoint column pass
   double dose = 1.0, slope = 0.0, thr = 0.0;
+};
+
+// Outputs of the image epilogue.
+struct EpiPtrs {
+  float *image = nullptr;         // [clip][P][N][N] or nullptr
+  const float *target = nullptr;  // [clip][N][N]; nullptr: no resist / loss / residual
+  float *G = nullptr;             // [clip][N][N] residual dL/dI
+  double *loss_part = nullptr;    // [clip][P][blocks]
 };
 
 constexpr int kTileCols = 4;
@@ -29,19 +38,25 @@ constexpr int kTileCols = 4;
 void prof_begin(const char *name, hipStream_t s);
 void prof_end(const char *name, hipStream_t s);
 
+// Threads per transform of length L (0 if L has no FFT plan).
 int pass_threads(int L);
-int run_mask_spectrum(const float *mask, cf2 *S1, cf2 *Mh, const PassGeo &g, const cf2 *twN, int nclips,
-                      hipStream_t s);
+
+int run_rows_fwd_real(const char *name, int L, const float *in, size_t in_clip, cf2 *out, int h, int Wp,
+                      const cf2 *tw, float scale, int nclips, hipStream_t s);
+int run_rows_inv_real(const char *name, int L, const cf2 *in, int h, int Wp, float *out, const EpiPtrs &ep,
+                      const PassGeo &g, const cf2 *tw, float scale, int nclips, hipStream_t s);
+int run_col_fft(const char *name, int L, int dir, const cf2 *in, cf2 *out, int nt, int in_h, int out_h,
+                const cf2 *tw, float scale, int nclips, hipStream_t s);
 int run_pass_y_fwd(const cf2 *bank, const cf2 *Mh, cf2 *Y, const PassGeo &g, const cf2 *twQ, int nclips,
                    hipStream_t s);
-int run_pass_x_fwd(const cf2 *Y, float *image, const float *target, float *G, double *loss_part,
-                   const PassGeo &g, const cf2 *twQ, int nclips, hipStream_t s);
-int run_pass_x_adj(cf2 *Y, const float *G, size_t g_clip_stride, const PassGeo &g, const cf2 *twQ, int nclips,
+int run_pass_x_fwd(const cf2 *Y, const EpiPtrs &ep, cf2 *Ib, const PassGeo &g, const cf2 *twQ, int nclips,
                    hipStream_t s);
+int run_pass_x_adj(cf2 *Y, const float *G, size_t g_clip_stride, const cf2 *Gband, const PassGeo &g,
+                   const cf2 *twQ, int nclips, hipStream_t s);
 int run_pass_y_adj(const cf2 *V, const cf2 *bank, double2 *part, const PassGeo &g, const cf2 *twQ, int nclips,
                    hipStream_t s);
-int run_grad_finish(const double2 *part, int nparts, cf2 *tmp, float *grad, const PassGeo &g, const cf2 *twN,
-                    int nclips, hipStream_t s);
+int run_grad_cols(const double2 *part, int nparts, cf2 *tmp, const PassGeo &g, const cf2 *twN, int nclips,
+                  hipStream_t s);
 int run_loss_reduce(const double *part, int n_per_clip, double *loss, int nclips, hipStream_t s);
 
 }  // namespace litho

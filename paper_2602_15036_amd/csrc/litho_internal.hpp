@@ -20,7 +20,7 @@ struct Workspace {
 struct CallLayout {
   PassGeo g;
   int nblk = 0;    // row-pass blocks per clip and plane (loss partials)
-  size_t b_S1 = 0, b_Mh = 0, b_Y = 0, b_G = 0, b_part = 0, b_loss = 0;
+  size_t b_S1 = 0, b_Mh = 0, b_Y = 0, b_G = 0, b_part = 0, b_loss = 0, b_X = 0;
   size_t per_clip = 0;
   int chunk = 1;   // clips per launch sequence
 };

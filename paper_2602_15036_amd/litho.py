@@ -100,6 +100,13 @@ class Bank:
                "litho_kernels_load")
         return cls(h)
 
+    def set_inner_grid(self, q: int = 0) -> None:
+        """Side of the per-kernel transform grid: 0 automatic, n full grid."""
+        _check(_lib.litho_kernels_set_inner_grid(self.handle, int(q)), "litho_kernels_set_inner_grid")
+        info = A.BankInfo()
+        _check(_lib.litho_kernels_info(self._h, C.byref(info)), "litho_kernels_info")
+        self.inner_grid = info.inner_grid
+
     def eigenvalues(self) -> np.ndarray:
         out = np.zeros((self.n_focus, self.K))
         _check(_lib.litho_kernels_eigenvalues(self._h, out.ctypes.data_as(C.POINTER(C.c_double))),

@@ -76,6 +76,7 @@ def test_vjp_mode_matches_oracle(L, clip64):
     bank = L.Bank.from_spec(spec)
     rng = np.random.default_rng(5)
     G = rng.standard_normal((2, 3, 64, 64)).astype(np.float32)
+    assert bank.inner_grid == 64
     _, _, grad = L.image_grad(bank, dev(masks), grad_image=dev(G), want_image=False)
     grad = grad.cpu().numpy()
     for i in range(2):
@@ -102,10 +103,11 @@ def test_autograd_functions(L, clip64):
     assert rel_l2(m2.grad[1].cpu().numpy(), 2.0 * g1) < GTOL
 
 
-@pytest.mark.parametrize("n", [256, 512])
-def test_gradient_parity_mid_sizes(L, n):
+@pytest.mark.parametrize("n,inner", [(128, 0), (256, 0), (256, 256), (512, 0)])
+def test_gradient_parity_mid_sizes(L, n, inner):
     spec = W.fd_clip_optics(n).with_(K=12)
     bank = L.Bank.from_spec(spec)
+    bank.set_inner_grid(inner)
     m = W.as_f32_exact(W.curvilinear_mask(n, 7))
     T = W.manhattan_target(n, 8)
     _, loss, grad = L.image_grad(bank, dev(m[None]), target=dev(T[None]), slope=SLOPE, threshold=THR,
@@ -115,10 +117,12 @@ def test_gradient_parity_mid_sizes(L, n):
     assert rel_l2(grad.cpu().numpy()[0], go) < GTOL
 
 
-def test_bench_launch_config_gradient(L):
+@pytest.mark.parametrize("inner", [0, 1024])
+def test_bench_launch_config_gradient(L, inner):
     # 1024 x 1024, K = 24, batch of 16: compare two clips of the batch in full
     spec = W.CONFIG2
     bank = L.Bank.from_spec(spec)
+    bank.set_inner_grid(inner)
     masks = np.stack([W.as_f32_exact(W.curvilinear_mask(1024, 1000 + s)) for s in range(16)])
     targets = np.stack([W.manhattan_target(1024, 1100 + s) for s in range(16)])
     _, loss, grad = L.image_grad(bank, dev(masks), target=dev(targets), slope=SLOPE, threshold=THR,
@@ -131,3 +135,17 @@ def test_bench_launch_config_gradient(L):
         assert rel_l2(grad[i], go) < GTOL
         # and on a 64 x 64 crop window
         assert rel_l2(grad[i][480:544, 480:544], go[480:544, 480:544]) < GTOL
+
+
+def test_vjp_mode_resampled_grid(L):
+    # the residual is low-passed to the intensity band on the inner grid
+    spec = W.fd_clip_optics(256).with_(K=10)
+    bank = L.Bank.from_spec(spec)
+    assert bank.inner_grid == 160
+    m = W.as_f32_exact(W.curvilinear_mask(256, 12))
+    rng = np.random.default_rng(9)
+    G = rng.standard_normal((1, 3, 256, 256)).astype(np.float32)
+    _, _, grad = L.image_grad(bank, dev(m[None]), grad_image=dev(G), want_image=False)
+    _, go, _ = O.gradient(m, None, _banks(spec, 10), SLOPE, THR,
+                          G_override=[G[0, p].astype(np.float64) for p in range(3)])
+    assert rel_l2(grad.cpu().numpy()[0], go) < GTOL

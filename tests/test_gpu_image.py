@@ -28,9 +28,13 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-def test_config1_parity_with_built_bank(L):
+@pytest.mark.parametrize("inner", ["auto", "full"])
+def test_config1_parity_with_built_bank(L, inner):
     spec = W.CONFIG1
     bank = L.Bank.from_spec(spec)
+    if inner == "full":
+        bank.set_inner_grid(128)
+    assert bank.inner_grid == (96 if inner == "auto" else 128)
     masks = np.stack([W.manhattan_mask(128, s) for s in range(8)])
     img = L.image(bank, dev(masks)).cpu().numpy()
     assert img.shape == (8, 1, 128, 128)
@@ -50,11 +54,12 @@ def test_config1_parity_with_oracle_bank(L):
         assert rel_l2(img[i, 0], O.image(masks[i], lam, phi)) < TOL
 
 
-@pytest.mark.parametrize("n", [64, 256, 512])
-def test_through_focus_dipole_parity(L, n):
+@pytest.mark.parametrize("n,inner", [(64, 0), (256, 0), (256, 256), (512, 0), (512, 512)])
+def test_through_focus_dipole_parity(L, n, inner):
     # three focus planes, dipole source, curvilinear grey masks, ragged batch of 3
     spec = W.fd_clip_optics(n)
     bank = L.Bank.from_spec(spec)
+    bank.set_inner_grid(inner)
     masks = np.stack([W.curvilinear_mask(n, 100 + s) for s in range(3)])
     m32 = W.as_f32_exact(masks)
     img = L.image(bank, dev(m32)).cpu().numpy()
@@ -90,10 +95,13 @@ def test_clear_and_dark_field(L):
     assert np.abs(img[1, 0]).max() == 0.0
 
 
-def test_bench_launch_config_sampled_pixels(L):
+@pytest.mark.parametrize("inner", [0, 768, 1024])
+def test_bench_launch_config_sampled_pixels(L, inner):
     # 1024 x 1024, K = 24, batch of 16 curvilinear clips: the bench workload
     spec = W.CONFIG2
     bank = L.Bank.from_spec(spec)
+    bank.set_inner_grid(inner)
+    assert bank.inner_grid == (640 if inner == 0 else inner)
     masks = np.stack([W.as_f32_exact(W.curvilinear_mask(1024, 1000 + s)) for s in range(16)])
     img = L.image(bank, dev(masks)).cpu().numpy()
     assert np.isfinite(img).all() and img.min() >= 0
@@ -124,3 +132,13 @@ def test_large_grid_sampled_pixels(L):
         lam, phi = O.socs_kernels(spec, F, K=24)
         ref = O.image_at(mh, lam, phi, 2048, ys, xs)
         assert rel_l2(img[p][ys, xs], ref) < TOL, p
+
+
+def test_inner_grid_validation(L):
+    bank = L.Bank.from_spec(W.CONFIG2.with_(n=256, K=4))
+    assert bank.inner_grid == 160
+    for bad in (96, 128, 300, 512):          # below 4b + 1 = 157, unsupported, above n
+        with pytest.raises(L.LithoError):
+            bank.set_inner_grid(bad)
+    bank.set_inner_grid(256)
+    assert bank.inner_grid == 256
