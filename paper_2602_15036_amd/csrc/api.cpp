@@ -341,8 +341,14 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
   g.Dp = (g.D + kTileCols - 1) / kTileCols * kTileCols;
   g.ntD = g.Dp / kTileCols;
   g.K = K_use; g.Kbank = h.K; g.P = h.n_focus; g.dose = h.dose;
-  g.kper = 4;
-  g.KC = (K_use + g.kper - 1) / g.kper;
+  // k-chunks of the adjoint column pass: enough blocks to fill the device
+  // (~2048), each chunk summing kper kernels in FP32 before the FP64 reduction.
+  {
+    const int want = int((2048 + size_t(g.nt) * batch - 1) / (size_t(g.nt) * batch));
+    const int kc = std::max(1, std::min(K_use, want));
+    g.kper = (K_use + kc - 1) / kc;
+    g.KC = (K_use + g.kper - 1) / g.kper;
+  }
   const bool resample = g.Q != g.N;
   // loss partials come from the row pass that applies the resist (N grid)
   L.nblk = g.N / (256 / pass_threads(g.N));

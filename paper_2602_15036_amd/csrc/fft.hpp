@@ -267,6 +267,36 @@ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 template <int L>
 constexpr int lds_len() { return L + L / 16; }
 
+// Ordering of the LDS exchange between passes.  A transform whose T threads
+// lie inside one wavefront only needs its own LDS writes to have landed
+// before its reads (DS instructions of a wavefront complete in order; the
+// explicit wait and the memory clobber also stop the compiler from moving
+// the reads above the writes).  Wider transforms synchronise the block.
+template <int T>
+__device__ __forceinline__ void xsync() {
+  if constexpr (T <= 64) {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Hides the twiddle-table pointer from loop-invariant code motion, so the
+// table loads of a transform inside a loop are issued per transform instead
+// of being hoisted into (and holding) registers for the whole loop.
+__device__ __forceinline__ const cf *opaque(const cf *p) {
+  int zero = 0;
+  asm volatile("" : "+s"(zero));
+  return p + zero;
+}
+
+// Same for a per-lane index: the LDS and table addresses derived from it are
+// then recomputed inside each transform rather than kept live across a loop.
+__device__ __forceinline__ int opaque_lane(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // One Stockham pass of radix R after passes whose radices multiply to S.
 template <int L, int T, int DIR, int R, int S, bool LAST>
 __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ buf, int t,
@@ -274,6 +304,7 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ b
   constexpr int E = L / T;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide the per-thread count");
+  const cf *twp = opaque(tw);
 #pragma unroll
   for (int mb = 0; mb < NB; ++mb) {
     const int j = t + T * mb;
@@ -285,7 +316,7 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ b
       constexpr int step = L / (S * R);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        cf w = tw[k * r * step];
+        cf w = twp[k * r * step];
         if constexpr (DIR > 0) w.y = -w.y;
         u[r] = cmul(u[r], w);
       }
@@ -301,10 +332,10 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ b
     }
   }
   if constexpr (!LAST) {
-    __syncthreads();
+    xsync<T>();
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = buf[lpad(t + T * i)];
-    __syncthreads();
+    xsync<T>();
   }
 }
 
@@ -321,11 +352,13 @@ __device__ __forceinline__ void fft_impl(cf (&v)[L / FftPlan<L>::T], cf *buf, in
 }
 
 // In-register FFT of length L (DIR = -1 forward, +1 inverse, unnormalised).
-// All threads of the block must call it (it contains block barriers).
-// buf: this transform's LDS region of lds_len<L>() complex values.
+// buf: this transform's private LDS region of lds_len<L>() complex values.
+// Transforms of at most 64 threads synchronise only their own wavefront, so
+// every thread of a wavefront must call it together (uniform control flow);
+// wider ones use block barriers and need the whole block.
 template <int L, int DIR>
 __device__ __forceinline__ void fft(cf (&v)[L / FftPlan<L>::T], cf *buf, int t, const cf *tw) {
-  fft_impl<L, DIR>(v, buf, t, tw, typename FftPlan<L>::R{});
+  fft_impl<L, DIR>(v, buf, opaque_lane(t), tw, typename FftPlan<L>::R{});
 }
 
 }  // namespace dev

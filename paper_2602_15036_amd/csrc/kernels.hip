@@ -81,23 +81,30 @@ __device__ __forceinline__ int pos_of_band_row(int r, int h, int L) {
   return r - h < 0 ? r - h + L : r - h;
 }
 
-// Copies rows y0..y0+RPB of a tiled band array [tiles][L][kC] into stage[RPB][Wp].
-template <int RPB>
-__device__ __forceinline__ void load_band_rows(const cf *__restrict__ src, int L, cf *stage, int Wp, int y0) {
-  const int chunk = RPB * kC;
-  for (int e = threadIdx.x; e < RPB * Wp; e += blockDim.x) {
-    const int jt = e / chunk, r = e % chunk, rr = r / kC, c = r % kC;
-    stage[rr * Wp + jt * kC + c] = src[(size_t(jt) * L + y0 + rr) * kC + c];
+// Band row |f| <= h of row y of a tiled array [tiles][L][kC], read straight
+// into the FFT register layout (thread t holds positions t + T*i).
+template <int L, int T>
+__device__ __forceinline__ void load_band_row(cf (&v)[L / T], const cf *__restrict__ src, int y, int t, int h) {
+  t = opaque_lane(t);
+#pragma unroll
+  for (int i = 0; i < L / T; ++i) {
+    const int j = band_row_of(t + T * i, L, h);
+    v[i] = j >= 0 ? src[(size_t(j >> 2) * L + y) * kC + (j & 3)] : cmake(0.f, 0.f);
   }
 }
 
-template <int RPB>
-__device__ __forceinline__ void store_band_rows(cf *__restrict__ dst, int L, const cf *stage, int Wp, int y0) {
-  const int chunk = RPB * kC;
-  for (int e = threadIdx.x; e < RPB * Wp; e += blockDim.x) {
-    const int jt = e / chunk, r = e % chunk, rr = r / kC, c = r % kC;
-    dst[(size_t(jt) * L + y0 + rr) * kC + c] = stage[rr * Wp + jt * kC + c];
+// Writes the band |f| <= h of a row held in the FFT register layout (scaled)
+// into row y of a tiled array, and zeros in its Wp - (2h+1) pad columns.
+template <int L, int T>
+__device__ __forceinline__ void store_band_row(const cf (&v)[L / T], cf *__restrict__ dst, int y, int t, int h,
+                                               int Wp, float scale) {
+  t = opaque_lane(t);
+#pragma unroll
+  for (int i = 0; i < L / T; ++i) {
+    const int j = band_row_of(t + T * i, L, h);
+    if (j >= 0) dst[(size_t(j >> 2) * L + y) * kC + (j & 3)] = cscale(v[i], scale);
   }
+  for (int j = 2 * h + 1 + t; j < Wp; j += T) dst[(size_t(j >> 2) * L + y) * kC + (j & 3)] = cmake(0.f, 0.f);
 }
 
 // Block-wide FP64 sum in fixed order; `red` holds blockDim.x doubles.
@@ -125,6 +132,10 @@ __device__ __forceinline__ double image_epilogue(const Epi &ep, const Geo &g, in
 }
 
 // ------------------------------------------------------------ real rows -> band
+// Row passes are wavefront-autonomous: each wavefront owns 64 / T rows, reads
+// and writes them straight from global memory and exchanges only through its
+// own LDS rows, so these kernels need no block barriers (T <= 64).
+//
 // out[clip][jt][y][c] = scale * sum_x in[y][x] exp(-2 pi i kx x / L), |kx| <= h,
 // kx = jt*kC + c - h; the Wp - (2h+1) pad columns are written as zeros.
 template <int L>
@@ -133,24 +144,14 @@ __global__ __launch_bounds__(256) void k_rows_fwd_real(const float *__restrict__
                                                        const cf *__restrict__ tw, float scale) {
   constexpr int T = FftPlan<L>::T, E = L / T, RPB = 256 / T;
   extern __shared__ cf smem[];
-  cf *stage = smem;                      // [RPB][Wp]
-  cf *xch = smem + RPB * Wp;             // [RPB][lds_len<L>]
   const int row = threadIdx.x / T, t = threadIdx.x % T;
-  const int y0 = blockIdx.x * RPB, y = y0 + row, clip = blockIdx.y;
+  const int y = blockIdx.x * RPB + row, clip = blockIdx.y;
   const float *src = in + clip * in_clip + size_t(y) * L;
   cf v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = cmake(src[t + T * i], 0.0f);
-  fft<L, -1>(v, xch + row * lds_len<L>(), t, tw);
-  cf *st = stage + row * Wp;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int j = band_row_of(t + T * i, L, h);
-    if (j >= 0) st[j] = cscale(v[i], scale);
-  }
-  for (int j = 2 * h + 1 + t; j < Wp; j += T) st[j] = cmake(0.f, 0.f);
-  __syncthreads();
-  store_band_rows<RPB>(out + size_t(clip) * (Wp / kC) * L * kC, L, stage, Wp, y0);
+  fft<L, -1>(v, smem + row * lds_len<L>(), t, tw);
+  store_band_row<L, T>(v, out + size_t(clip) * (Wp / kC) * L * kC, y, t, h, Wp, scale);
 }
 
 // ------------------------------------------------------------ band rows -> real rows
@@ -162,21 +163,11 @@ __global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in
                                                        const cf *__restrict__ tw, float scale) {
   constexpr int T = FftPlan<L>::T, E = L / T, RPB = 256 / T;
   extern __shared__ cf smem[];
-  cf *stage = smem;
-  cf *xch = smem + RPB * Wp;
   const int row = threadIdx.x / T, t = threadIdx.x % T;
-  const int y0 = blockIdx.x * RPB, y = y0 + row, clip = blockIdx.y;
-  load_band_rows<RPB>(in + size_t(clip) * (Wp / kC) * L * kC, L, stage, Wp, y0);
-  __syncthreads();
-  const cf *st = stage + row * Wp;
+  const int y = blockIdx.x * RPB + row, clip = blockIdx.y;
   cf v[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int j = band_row_of(t + T * i, L, h);
-    v[i] = j >= 0 ? st[j] : cmake(0.f, 0.f);
-  }
-  __syncthreads();
-  fft<L, +1>(v, xch + row * lds_len<L>(), t, tw);
+  load_band_row<L, T>(v, in + size_t(clip) * (Wp / kC) * L * kC, y, t, h);
+  fft<L, +1>(v, smem + row * lds_len<L>(), t, tw);
   if constexpr (MODE == 0) {
     float *dst = out + (size_t(clip) * L + y) * L;
 #pragma unroll
@@ -275,32 +266,24 @@ __global__ __launch_bounds__(512) void k_pass_y_fwd(const cf *__restrict__ bank,
 // ------------------------------------------------------------ forward row pass
 // I_Q(y, x) = dose * sum_k |sum_kx Y_k(y, kx) exp(+2 pi i kx x / Q)|^2.
 // OUT 0 (Q == N): image / resist epilogue.  OUT 1 (Q < N): forward row DFT of
-// the I_Q row, keep |gx| <= 2b, scale 1/Q^2, store tiled [ntD][Q][kC] in Ib.
+// the I_Q row, keep |gx| <= 2b, scale dose/Q^2, store tiled [ntD][Q][kC] in Ib.
 template <int Q, int OUT>
 __global__ __launch_bounds__(256) void k_pass_x_fwd(const cf *__restrict__ Y, Epi ep, cf *__restrict__ Ib, Geo g,
                                                     const cf *__restrict__ tw) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
   extern __shared__ cf smem[];
-  const int Wst = OUT == 0 ? g.Bp : max(g.Bp, g.Dp);
-  cf *stage = smem;
-  cf *xch = smem + RPB * Wst;
   const int row = threadIdx.x / T, t = threadIdx.x % T;
-  const int y0 = blockIdx.x * RPB, y = y0 + row, clip = blockIdx.y;
+  const int y = blockIdx.x * RPB + row, clip = blockIdx.y;
+  cf *xch = smem + row * lds_len<Q>();
   float acc[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) acc[i] = 0.f;
-  const cf *st = stage + row * g.Bp;
+  const size_t kstride = size_t(g.nt) * Q * kC;
+  const cf *yc = Y + size_t(clip) * g.K * kstride;
   for (int k = 0; k < g.K; ++k) {
-    load_band_rows<RPB>(Y + (size_t(clip) * g.K + k) * g.nt * size_t(Q) * kC, Q, stage, g.Bp, y0);
-    __syncthreads();
     cf v[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int j = band_row_of(t + T * i, Q, g.b);
-      v[i] = j >= 0 ? st[j] : cmake(0.f, 0.f);
-    }
-    __syncthreads();
-    fft<Q, +1>(v, xch + row * lds_len<Q>(), t, tw);
+    load_band_row<Q, T>(v, yc + k * kstride, y, t, g.b);
+    fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) acc[i] += cabs2(v[i]);
   }
@@ -316,24 +299,16 @@ __global__ __launch_bounds__(256) void k_pass_x_fwd(const cf *__restrict__ Y, Ep
     cf v[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = cmake(acc[i], 0.f);
-    fft<Q, -1>(v, xch + row * lds_len<Q>(), t, tw);
-    const float sc = g.dose / (float(Q) * float(Q));
-    cf *so = stage + row * g.Dp;
-    const int h2 = 2 * g.b;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int j = band_row_of(t + T * i, Q, h2);
-      if (j >= 0) so[j] = cscale(v[i], sc);
-    }
-    for (int j = g.D + t; j < g.Dp; j += T) so[j] = cmake(0.f, 0.f);
-    __syncthreads();
-    store_band_rows<RPB>(Ib + size_t(clip) * g.ntD * size_t(Q) * kC, Q, stage, g.Dp, y0);
+    fft<Q, -1>(v, xch, t, tw);
+    store_band_row<Q, T>(v, Ib + size_t(clip) * g.ntD * size_t(Q) * kC, y, t, 2 * g.b, g.Dp,
+                         g.dose / (float(Q) * float(Q)));
   }
 }
 
 // ------------------------------------------------------------ adjoint row pass
 // V_k(y, kx) = sum_x G(y, x) E'_k(y, x) exp(-2 pi i kx x / Q), |kx| <= b,
-// E'_k recomputed from Y_k; V_k overwrites Y_k.
+// E'_k recomputed from Y_k; V_k overwrites Y_k (each row is owned by one
+// wavefront, which reads it completely before writing it).
 // GIN 0: G is a real [Q][Q] array per clip (Q == N), rows strided by Q.
 // GIN 1: G is a band [ntD][Q][kC] (|gx| <= 2b) per clip; its row is synthesised.
 template <int Q, int GIN>
@@ -342,63 +317,39 @@ __global__ __launch_bounds__(256) void k_pass_x_adj(cf *__restrict__ Y, const fl
                                                     const cf *__restrict__ tw) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
   extern __shared__ cf smem[];
-  const int Wst = GIN == 0 ? g.Bp : max(g.Bp, g.Dp);
-  cf *stage = smem;
-  cf *xch = smem + RPB * Wst;
   const int row = threadIdx.x / T, t = threadIdx.x % T;
-  const int y0 = blockIdx.x * RPB, y = y0 + row, clip = blockIdx.y;
+  const int y = blockIdx.x * RPB + row, clip = blockIdx.y;
+  cf *xch = smem + row * lds_len<Q>();
   float gr[E];
   if constexpr (GIN == 0) {
     const float *gsrc = Greal + clip * g_clip_stride + size_t(y) * Q;
 #pragma unroll
     for (int i = 0; i < E; ++i) gr[i] = gsrc[t + T * i] * g.dose;
   } else {
-    load_band_rows<RPB>(Gband + size_t(clip) * g.ntD * size_t(Q) * kC, Q, stage, g.Dp, y0);
-    __syncthreads();
-    const cf *sg = stage + row * g.Dp;
-    const int h2 = 2 * g.b;
     cf v[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int j = band_row_of(t + T * i, Q, h2);
-      v[i] = j >= 0 ? sg[j] : cmake(0.f, 0.f);
-    }
-    __syncthreads();
-    fft<Q, +1>(v, xch + row * lds_len<Q>(), t, tw);
+    load_band_row<Q, T>(v, Gband + size_t(clip) * g.ntD * size_t(Q) * kC, y, t, 2 * g.b);
+    fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) gr[i] = v[i].x * g.dose;
   }
-  cf *st = stage + row * g.Bp;
+  const size_t kstride = size_t(g.nt) * Q * kC;
+  cf *yc = Y + size_t(clip) * g.K * kstride;
   for (int k = 0; k < g.K; ++k) {
-    cf *yk = Y + (size_t(clip) * g.K + k) * g.nt * size_t(Q) * kC;
-    load_band_rows<RPB>(yk, Q, stage, g.Bp, y0);
-    __syncthreads();
     cf v[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int j = band_row_of(t + T * i, Q, g.b);
-      v[i] = j >= 0 ? st[j] : cmake(0.f, 0.f);
-    }
-    __syncthreads();
-    fft<Q, +1>(v, xch + row * lds_len<Q>(), t, tw);
+    load_band_row<Q, T>(v, yc + k * kstride, y, t, g.b);
+    fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = cscale(v[i], gr[i]);
-    fft<Q, -1>(v, xch + row * lds_len<Q>(), t, tw);
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int j = band_row_of(t + T * i, Q, g.b);
-      if (j >= 0) st[j] = v[i];
-    }
-    for (int j = g.B + t; j < g.Bp; j += T) st[j] = cmake(0.f, 0.f);
-    __syncthreads();
-    store_band_rows<RPB>(yk, Q, stage, g.Bp, y0);
-    __syncthreads();
+    fft<Q, -1>(v, xch, t, tw);
+    store_band_row<Q, T>(v, yc + k * kstride, y, t, g.b, g.Bp, 1.0f);
   }
 }
 
 // ------------------------------------------------------------ adjoint column pass
 // part[clip][p*KC + kc][jt][ky][c] = sum_{k in chunk} conj(Phi'_k) * sum_y V_k(y, j) exp(-2 pi i ky y / Q)
-template <int Q, int U>
+// The chunk sum is accumulated in FP32 in the FFT register layout (band rows
+// only) and stored in FP64; chunks and planes are summed in FP64 later.
+template <int Q>
 __global__ __launch_bounds__(512) void k_pass_y_adj(const cf *__restrict__ V, const cf *__restrict__ bank,
                                                     double2 *__restrict__ part, Geo g,
                                                     const cf *__restrict__ tw) {
@@ -407,46 +358,37 @@ __global__ __launch_bounds__(512) void k_pass_y_adj(const cf *__restrict__ V, co
   const int c = threadIdx.x / T, t = threadIdx.x % T;
   const int jt = blockIdx.x, kc = blockIdx.y, clip = blockIdx.z;
   cf *buf = smem + c * lds_len<Q>();
-  const int nE = g.B * kC;
-  double2 acc[U];  // band entries e = threadIdx.x + blockDim.x * u, u < U
+  cf acc[E];
 #pragma unroll
-  for (int u = 0; u < U; ++u) acc[u] = make_double2(0.0, 0.0);
+  for (int i = 0; i < E; ++i) acc[i] = cmake(0.f, 0.f);
   const int k0 = kc * g.kper, k1 = min(g.K, k0 + g.kper);
   for (int k = k0; k < k1; ++k) {
     const cf *src = V + ((size_t(clip) * g.K + k) * g.nt + jt) * size_t(Q) * kC;
-    for (int e = threadIdx.x; e < Q * kC; e += blockDim.x)
+    for (int e = opaque_lane(threadIdx.x); e < Q * kC; e += blockDim.x)
       smem[(e % kC) * lds_len<Q>() + lpad(e / kC)] = src[e];
     __syncthreads();
+    const int tt = opaque_lane(t);
     cf v[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = buf[lpad(t + T * i)];
+    for (int i = 0; i < E; ++i) v[i] = buf[lpad(tt + T * i)];
     __syncthreads();
     fft<Q, -1>(v, buf, t, tw);
+    const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + jt) * g.B * kC + c;
+    const int t2 = opaque_lane(t);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      const int r = band_row_of(t + T * i, Q, g.b);
-      if (r >= 0) buf[lpad(r)] = v[i];
-    }
-    __syncthreads();
-    const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + jt) * g.B * kC;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = threadIdx.x + blockDim.x * u;
-      if (e < nE) {
-        const cf val = smem[(e % kC) * lds_len<Q>() + lpad(e / kC)];
-        const cf phv = ph[e];
-        // conj(phi) * val
-        acc[u].x += double(phv.x) * double(val.x) + double(phv.y) * double(val.y);
-        acc[u].y += double(phv.x) * double(val.y) - double(phv.y) * double(val.x);
+      const int r = band_row_of(t2 + T * i, Q, g.b);
+      if (r >= 0) {
+        const cf w = ph[r * kC];
+        acc[i] = make_float2(acc[i].x + w.x * v[i].x + w.y * v[i].y, acc[i].y + w.x * v[i].y - w.y * v[i].x);
       }
     }
-    __syncthreads();
   }
-  double2 *dst = part + ((size_t(clip) * g.P * g.KC + size_t(g.p) * g.KC + kc) * g.nt + jt) * size_t(nE);
+  double2 *dst = part + ((size_t(clip) * g.P * g.KC + size_t(g.p) * g.KC + kc) * g.nt + jt) * size_t(g.B) * kC + c;
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int e = threadIdx.x + blockDim.x * u;
-    if (e < nE) dst[e] = acc[u];
+  for (int i = 0; i < E; ++i) {
+    const int r = band_row_of(t + T * i, Q, g.b);
+    if (r >= 0) dst[r * kC] = make_double2(acc[i].x, acc[i].y);
   }
 }
 
@@ -563,7 +505,7 @@ template <int L>
 int rows_fwd_real_l(const char *name, const float *in, size_t in_clip, cf *out, int h, int Wp, const cf *tw,
                     float scale, int nclips, hipStream_t s) {
   constexpr int T = FftPlan<L>::T, RPB = 256 / T;
-  size_t sh = (size_t(RPB) * Wp + size_t(RPB) * lds_len<L>()) * sizeof(cf);
+  size_t sh = size_t(RPB) * lds_len<L>() * sizeof(cf);
   return launch(name, KPTR(dev::k_rows_fwd_real<L>), dim3(L / RPB, nclips), sh, s, [&] {
     hipLaunchKernelGGL(dev::k_rows_fwd_real<L>, dim3(L / RPB, nclips), dim3(256), sh, s, in, in_clip, out, h, Wp,
                        tw, scale);
@@ -574,7 +516,7 @@ template <int L, int MODE>
 int rows_inv_real_l(const char *name, const cf *in, int h, int Wp, float *out, const EpiPtrs &ep,
                     const PassGeo &pg, const cf *tw, float scale, int nclips, hipStream_t s) {
   constexpr int T = FftPlan<L>::T, RPB = 256 / T;
-  size_t sh = (size_t(RPB) * Wp + size_t(RPB) * lds_len<L>()) * sizeof(cf);
+  size_t sh = size_t(RPB) * lds_len<L>() * sizeof(cf);
   sh = std::max(sh, size_t(256) * sizeof(double));
   Geo g = to_geo(pg);
   Epi e = to_epi(ep);
@@ -614,8 +556,7 @@ int pass_x_fwd_q(const cf *Y, const EpiPtrs &ep, cf *Ib, const PassGeo &pg, cons
   Geo g = to_geo(pg);
   Epi e = to_epi(ep);
   const bool band = g.Q != g.N;
-  const int Wst = band ? std::max(g.Bp, g.Dp) : g.Bp;
-  size_t sh = (size_t(RPB) * Wst + size_t(RPB) * lds_len<Q>()) * sizeof(cf);
+  size_t sh = size_t(RPB) * lds_len<Q>() * sizeof(cf);
   sh = std::max(sh, size_t(256) * sizeof(double));
   if (!band)
     return launch("pass_x_fwd", KPTR(dev::k_pass_x_fwd<Q, 0>), dim3(Q / RPB, nclips), sh, s, [&] {
@@ -632,8 +573,7 @@ int pass_x_adj_q(cf *Y, const float *G, size_t g_clip_stride, const cf *Gband, c
   constexpr int T = FftPlan<Q>::T, RPB = 256 / T;
   Geo g = to_geo(pg);
   const bool band = Gband != nullptr;
-  const int Wst = band ? std::max(g.Bp, g.Dp) : g.Bp;
-  size_t sh = (size_t(RPB) * Wst + size_t(RPB) * lds_len<Q>()) * sizeof(cf);
+  size_t sh = size_t(RPB) * lds_len<Q>() * sizeof(cf);
   if (!band)
     return launch("pass_x_adj", KPTR(dev::k_pass_x_adj<Q, 0>), dim3(Q / RPB, nclips), sh, s, [&] {
       hipLaunchKernelGGL((dev::k_pass_x_adj<Q, 0>), dim3(Q / RPB, nclips), dim3(256), sh, s, Y, G, g_clip_stride,
@@ -645,31 +585,15 @@ int pass_x_adj_q(cf *Y, const float *G, size_t g_clip_stride, const cf *Gband, c
   });
 }
 
-template <int Q, int U>
-int pass_y_adj_qu(const cf *V, const cf *bank, double2 *part, const PassGeo &pg, const cf *twQ, int nclips,
-                  hipStream_t s) {
-  constexpr int T = FftPlan<Q>::T;
-  Geo g = to_geo(pg);
-  size_t sh = size_t(kC) * lds_len<Q>() * sizeof(cf);
-  return launch("pass_y_adj", KPTR(dev::k_pass_y_adj<Q, U>), dim3(g.nt, g.KC, nclips), sh, s, [&] {
-    hipLaunchKernelGGL((dev::k_pass_y_adj<Q, U>), dim3(g.nt, g.KC, nclips), dim3(kC * T), sh, s, V, bank, part,
-                       g, twQ);
-  });
-}
-
-// The accumulator holds ceil(B / T) band entries per thread; pick the
-// smallest register array that covers them.
 template <int Q>
 int pass_y_adj_q(const cf *V, const cf *bank, double2 *part, const PassGeo &pg, const cf *twQ, int nclips,
                  hipStream_t s) {
   constexpr int T = FftPlan<Q>::T;
-  const int need = (pg.B + T - 1) / T;
-  if (need <= 2) return pass_y_adj_qu<Q, 2>(V, bank, part, pg, twQ, nclips, s);
-  if (need <= 4) return pass_y_adj_qu<Q, 4>(V, bank, part, pg, twQ, nclips, s);
-  if (need <= 8) return pass_y_adj_qu<Q, 8>(V, bank, part, pg, twQ, nclips, s);
-  if (need <= 16) return pass_y_adj_qu<Q, 16>(V, bank, part, pg, twQ, nclips, s);
-  set_error("pass_y_adj: band side %d too large for %d threads per column", pg.B, T);
-  return LITHO_E_UNSUPPORTED;
+  Geo g = to_geo(pg);
+  size_t sh = size_t(kC) * lds_len<Q>() * sizeof(cf);
+  return launch("pass_y_adj", KPTR(dev::k_pass_y_adj<Q>), dim3(g.nt, g.KC, nclips), sh, s, [&] {
+    hipLaunchKernelGGL(dev::k_pass_y_adj<Q>, dim3(g.nt, g.KC, nclips), dim3(kC * T), sh, s, V, bank, part, g, twQ);
+  });
 }
 
 template <int N>
