@@ -129,20 +129,17 @@ static int upload_bank(litho_bank *bk) {
 
 namespace litho {
 
-// Twiddle table exp(-2 pi i e / L), computed in FP64 and rounded once.
+// Per-pass twiddle table of the length-L FFT plan, uploaded once per bank.
 int make_twiddles(int L, float2 **out) {
-  std::vector<float2> tw(L);
-  for (int e = 0; e < L; ++e) {
-    const double a = -2.0 * M_PI * double(e) / double(L);
-    tw[e] = make_float2(float(std::cos(a)), float(std::sin(a)));
-  }
-  if (hipMalloc(out, L * sizeof(float2)) != hipSuccess) {
+  std::vector<float2> tw;
+  LITHO_TRY(twiddle_table(L, tw));
+  if (hipMalloc(out, tw.size() * sizeof(float2)) != hipSuccess) {
     (void)hipGetLastError();
     *out = nullptr;
     set_error("litho: cannot allocate the twiddle table");
     return LITHO_E_NOMEM;
   }
-  LITHO_HIP_TRY(hipMemcpy(*out, tw.data(), L * sizeof(float2), hipMemcpyHostToDevice));
+  LITHO_HIP_TRY(hipMemcpy(*out, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
   return LITHO_OK;
 }
 

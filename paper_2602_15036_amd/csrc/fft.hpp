@@ -261,11 +261,35 @@ template <> struct FftPlan<1536> { static constexpr int T = 64; using R = Radice
 template <> struct FftPlan<2560> { static constexpr int T = 64; using R = Radices<10, 8, 8, 4>; };
 template <> struct FftPlan<3072> { static constexpr int T = 64; using R = Radices<16, 16, 12>; };
 
-// LDS index with one pad slot every 16 complex values (breaks the power-of-two
-// strides of the Stockham scatter).
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// LDS index with one pad slot every 32 complex values, and 4 more slots
+// between the regions of neighbouring transforms: breaks the power-of-two
+// strides of the Stockham scatter across 64 four-byte banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
 template <int L>
-constexpr int lds_len() { return L + L / 16; }
+constexpr int lds_len() { return L + L / 32 + 4; }
+
+// Twiddle table layout.  Pass p (radix R after radices multiplying to S > 1)
+// owns S * (R - 1) consecutive entries starting at tw_offset<p>; entry
+// [k][r - 1] = exp(-2 pi i k r / (S R)).  A butterfly therefore reads its
+// R - 1 twiddles from one base address.
+template <int S, int... Rs>
+struct TwSize;
+template <int S>
+struct TwSize<S> {
+  static constexpr int value = 0;
+};
+template <int S, int R, int... Rest>
+struct TwSize<S, R, Rest...> {
+  static constexpr int value = (S > 1 ? S * (R - 1) : 0) + TwSize<S * R, Rest...>::value;
+};
+template <int L, typename Rad>
+struct TwTable;
+template <int L, int... Rs>
+struct TwTable<L, Radices<Rs...>> {
+  static constexpr int size = TwSize<1, Rs...>::value;
+};
+template <int L>
+constexpr int twiddle_table_size() { return TwTable<L, typename FftPlan<L>::R>::size; }
 
 // Ordering of the LDS exchange between passes.  A transform whose T threads
 // lie inside one wavefront only needs its own LDS writes to have landed
@@ -297,8 +321,9 @@ __device__ __forceinline__ int opaque_lane(int x) {
   return x;
 }
 
-// One Stockham pass of radix R after passes whose radices multiply to S.
-template <int L, int T, int DIR, int R, int S, bool LAST>
+// One Stockham pass of radix R after passes whose radices multiply to S;
+// its twiddles start at entry OFF of the table.
+template <int L, int T, int DIR, int R, int S, int OFF, bool LAST>
 __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ buf, int t,
                                               const cf *__restrict__ tw) {
   constexpr int E = L / T;
@@ -312,11 +337,10 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ b
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[mb + r * NB];
     if constexpr (S > 1) {
-      const int k = j % S;
-      constexpr int step = L / (S * R);
+      const cf *tb = twp + OFF + (j % S) * (R - 1);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        cf w = twp[k * r * step];
+        cf w = tb[r - 1];
         if constexpr (DIR > 0) w.y = -w.y;
         u[r] = cmul(u[r], w);
       }
@@ -339,16 +363,46 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ b
   }
 }
 
-template <int L, int T, int DIR, int S, int R, int... Rest>
+template <int L, int T, int DIR, int S, int OFF, int R, int... Rest>
 __device__ __forceinline__ void run_passes(cf (&v)[L / T], cf *buf, int t, const cf *tw) {
-  stockham_pass<L, T, DIR, R, S, sizeof...(Rest) == 0>(v, buf, t, tw);
-  if constexpr (sizeof...(Rest) > 0) run_passes<L, T, DIR, S * R, Rest...>(v, buf, t, tw);
+  stockham_pass<L, T, DIR, R, S, OFF, sizeof...(Rest) == 0>(v, buf, t, tw);
+  if constexpr (sizeof...(Rest) > 0)
+    run_passes<L, T, DIR, S * R, OFF + (S > 1 ? S * (R - 1) : 0), Rest...>(v, buf, t, tw);
 }
 
 template <int L, int DIR, int... Rs>
 __device__ __forceinline__ void fft_impl(cf (&v)[L / FftPlan<L>::T], cf *buf, int t, const cf *tw,
                                          Radices<Rs...>) {
-  run_passes<L, FftPlan<L>::T, DIR, 1, Rs...>(v, buf, t, tw);
+  run_passes<L, FftPlan<L>::T, DIR, 1, 0, Rs...>(v, buf, t, tw);
+}
+
+// Host: fills the table of FftPlan<L> (FP64 angles, rounded once to FP32).
+template <int S, int... Rs>
+struct TwFill;
+template <int S>
+struct TwFill<S> {
+  static void run(float2 *, int) {}
+};
+template <int S, int R, int... Rest>
+struct TwFill<S, R, Rest...> {
+  static void run(float2 *out, int off) {
+    if (S > 1) {
+      for (int k = 0; k < S; ++k)
+        for (int r = 1; r < R; ++r) {
+          const double a = -2.0 * 3.14159265358979323846 * double(k) * double(r) / double(S * R);
+          out[off + k * (R - 1) + (r - 1)] = make_float2(float(__builtin_cos(a)), float(__builtin_sin(a)));
+        }
+    }
+    TwFill<S * R, Rest...>::run(out, off + (S > 1 ? S * (R - 1) : 0));
+  }
+};
+template <int L, int... Rs>
+void fill_twiddles_impl(float2 *out, Radices<Rs...>) {
+  TwFill<1, Rs...>::run(out, 0);
+}
+template <int L>
+void fill_twiddles(float2 *out) {
+  fill_twiddles_impl<L>(out, typename FftPlan<L>::R{});
 }
 
 // In-register FFT of length L (DIR = -1 forward, +1 inverse, unnormalised).

@@ -40,6 +40,9 @@
 #include "fft.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
+#include <vector>
+
 namespace litho {
 namespace dev {
 
@@ -263,12 +266,19 @@ __global__ __launch_bounds__(512) void k_pass_y_fwd(const cf *__restrict__ bank,
     dst[e] = smem[(e % kC) * lds_len<Q>() + lpad(e / kC)];
 }
 
+// Occupancy target of the k-loop row passes: four wavefronts per SIMD (128
+// VGPRs) while a thread holds at most 20 values, two beyond.
+template <int Q>
+struct RowWaves {
+  static constexpr int value = Q / FftPlan<Q>::T <= 20 ? 4 : 2;
+};
+
 // ------------------------------------------------------------ forward row pass
 // I_Q(y, x) = dose * sum_k |sum_kx Y_k(y, kx) exp(+2 pi i kx x / Q)|^2.
 // OUT 0 (Q == N): image / resist epilogue.  OUT 1 (Q < N): forward row DFT of
 // the I_Q row, keep |gx| <= 2b, scale dose/Q^2, store tiled [ntD][Q][kC] in Ib.
 template <int Q, int OUT>
-__global__ __launch_bounds__(256) void k_pass_x_fwd(const cf *__restrict__ Y, Epi ep, cf *__restrict__ Ib, Geo g,
+__global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf *__restrict__ Y, Epi ep, cf *__restrict__ Ib, Geo g,
                                                     const cf *__restrict__ tw) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
   extern __shared__ cf smem[];
@@ -312,7 +322,7 @@ __global__ __launch_bounds__(256) void k_pass_x_fwd(const cf *__restrict__ Y, Ep
 // GIN 0: G is a real [Q][Q] array per clip (Q == N), rows strided by Q.
 // GIN 1: G is a band [ntD][Q][kC] (|gx| <= 2b) per clip; its row is synthesised.
 template <int Q, int GIN>
-__global__ __launch_bounds__(256) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Greal,
+__global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Greal,
                                                     size_t g_clip_stride, const cf *__restrict__ Gband, Geo g,
                                                     const cf *__restrict__ tw) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
@@ -704,6 +714,23 @@ int run_loss_reduce(const double *part, int n_per_clip, double *loss, int nclips
   return launch("loss_reduce", KPTR(dev::k_loss_reduce), dim3(nclips), 0, s, [&] {
     hipLaunchKernelGGL(dev::k_loss_reduce, dim3(nclips), dim3(256), 0, s, part, n_per_clip, loss);
   });
+}
+
+int twiddle_table(int L, std::vector<float2> &out) {
+  switch (L) {
+#define LITHO_TW(X)                                      \
+  case X:                                                \
+    out.assign(std::max(1, dev::twiddle_table_size<X>()), make_float2(0.f, 0.f)); \
+    dev::fill_twiddles<X>(out.data());                   \
+    return LITHO_OK;
+    LITHO_TW(64) LITHO_TW(96) LITHO_TW(128) LITHO_TW(160) LITHO_TW(256) LITHO_TW(320) LITHO_TW(512) LITHO_TW(640)
+    LITHO_TW(768) LITHO_TW(1024) LITHO_TW(1280) LITHO_TW(1536) LITHO_TW(2048) LITHO_TW(2560) LITHO_TW(3072)
+    LITHO_TW(4096)
+#undef LITHO_TW
+    default:
+      set_error("no FFT plan for length %d", L);
+      return LITHO_E_UNSUPPORTED;
+  }
 }
 
 int pass_threads(int L) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <vector>
 
 #include "common.hpp"
 
@@ -40,6 +41,8 @@ void prof_end(const char *name, hipStream_t s);
 
 // Threads per transform of length L (0 if L has no FFT plan).
 int pass_threads(int L);
+// Per-pass twiddle table of the length-L plan (see fft.hpp).
+int twiddle_table(int L, std::vector<float2> &out);
 
 int run_rows_fwd_real(const char *name, int L, const float *in, size_t in_clip, cf2 *out, int h, int Wp,
                       const cf2 *tw, float scale, int nclips, hipStream_t s);
