@@ -186,84 +186,93 @@ __global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in
   }
 }
 
-// ------------------------------------------------------------ generic column pass
+// ------------------------------------------------------------ column passes
+// A column pass runs one length-L transform per tile column.  A block holds
+// ColBlock<L>::tiles tiles (4 columns each, T threads per column); every
+// thread reads and writes its own column entries straight from global memory
+// (positions t + T*i), and exchanges only through its column's LDS region.
+template <int L>
+struct ColBlock {
+  static constexpr int T = FftPlan<L>::T;
+  static constexpr int threads = 4 * T > 256 ? 4 * T : 256;
+  static constexpr int tiles = threads / (4 * T);
+};
+
+// Column (tile, c) handled by this thread, and whether the tile exists.
+template <int L>
+__device__ __forceinline__ void col_coords(int nt, int &jt, int &c, int &t, bool &valid) {
+  constexpr int T = FftPlan<L>::T;
+  const int col = threadIdx.x / T;
+  t = threadIdx.x % T;
+  c = col % kC;
+  jt = blockIdx.x * ColBlock<L>::tiles + col / kC;
+  valid = jt < nt;
+  if (!valid) jt = nt - 1;  // keep addresses in range; results are not stored
+}
+
 // For each tile column: a length-L DFT along the rows.  Input rows are either
 // all L positions (in_h < 0) or a centred band of 2*in_h+1 rows placed at
 // frequency positions (row - in_h) mod L; outputs are either all L rows
 // (out_h < 0) or the centred band |f| <= out_h.  Values are scaled by `scale`.
 template <int L, int DIR>
-__global__ __launch_bounds__(512) void k_col_fft(const cf *__restrict__ in, cf *__restrict__ out, int nt,
-                                                 int in_h, int out_h, size_t in_clip, size_t out_clip,
-                                                 const cf *__restrict__ tw, float scale) {
+__global__ __launch_bounds__(ColBlock<L>::threads) void k_col_fft(const cf *__restrict__ in, cf *__restrict__ out,
+                                                                 int nt, int in_h, int out_h, size_t in_clip,
+                                                                 size_t out_clip, const cf *__restrict__ tw,
+                                                                 float scale) {
   constexpr int T = FftPlan<L>::T, E = L / T;
   extern __shared__ cf smem[];
-  const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int jt = blockIdx.x, clip = blockIdx.y;
-  cf *buf = smem + c * lds_len<L>();
+  int jt, c, t;
+  bool valid;
+  col_coords<L>(nt, jt, c, t, valid);
+  const int clip = blockIdx.y;
+  cf *buf = smem + (threadIdx.x / T) * lds_len<L>();
   const int rin = in_h < 0 ? L : 2 * in_h + 1;
   const int rout = out_h < 0 ? L : 2 * out_h + 1;
-  const cf *src = in + clip * in_clip + size_t(jt) * rin * kC;
-  cf *dst = out + clip * out_clip + size_t(jt) * rout * kC;
-  if (in_h >= 0) {
-    for (int e = threadIdx.x; e < kC * L; e += blockDim.x)
-      smem[(e / L) * lds_len<L>() + lpad(e % L)] = cmake(0.f, 0.f);
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < rin * kC; e += blockDim.x) {
-    const int r = e / kC, cc = e % kC;
-    const int pos = in_h < 0 ? r : pos_of_band_row(r, in_h, L);
-    smem[cc * lds_len<L>() + lpad(pos)] = src[e];
-  }
-  __syncthreads();
+  const cf *src = in + clip * in_clip + size_t(jt) * rin * kC + c;
+  cf *dst = out + clip * out_clip + size_t(jt) * rout * kC + c;
   cf v[E];
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = buf[lpad(t + T * i)];
-  __syncthreads();
+  for (int i = 0; i < E; ++i) {
+    const int pos = t + T * i;
+    const int r = in_h < 0 ? pos : band_row_of(pos, L, in_h);
+    v[i] = r >= 0 ? src[r * kC] : cmake(0.f, 0.f);
+  }
   fft<L, DIR>(v, buf, t, tw);
+  if (!valid) return;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int pos = t + T * i;
     const int r = out_h < 0 ? pos : band_row_of(pos, L, out_h);
-    if (r >= 0) buf[lpad(r)] = cscale(v[i], scale);
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < rout * kC; e += blockDim.x) {
-    const int r = e / kC, cc = e % kC;
-    dst[e] = smem[cc * lds_len<L>() + lpad(r)];
+    if (r >= 0) dst[r * kC] = cscale(v[i], scale);
   }
 }
 
 // ------------------------------------------------------------ forward column pass
 // Y_k[jt][y][c] = sum_ky Phi'_k(ky, j) Mh(ky, j) exp(+2 pi i ky y / Q).
 template <int Q>
-__global__ __launch_bounds__(512) void k_pass_y_fwd(const cf *__restrict__ bank, const cf *__restrict__ Mh,
-                                                    cf *__restrict__ Y, Geo g, const cf *__restrict__ tw) {
+__global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_fwd(const cf *__restrict__ bank,
+                                                                    const cf *__restrict__ Mh, cf *__restrict__ Y,
+                                                                    Geo g, const cf *__restrict__ tw) {
   constexpr int T = FftPlan<Q>::T, E = Q / T;
   extern __shared__ cf smem[];
-  const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int jt = blockIdx.x, k = blockIdx.y, clip = blockIdx.z;
-  cf *buf = smem + c * lds_len<Q>();
-  for (int e = threadIdx.x; e < kC * Q; e += blockDim.x)
-    smem[(e / Q) * lds_len<Q>() + lpad(e % Q)] = cmake(0.f, 0.f);
-  __syncthreads();
-  const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + jt) * g.B * kC;
-  const cf *mh = Mh + (size_t(clip) * g.nt + jt) * g.B * kC;
-  for (int e = threadIdx.x; e < g.B * kC; e += blockDim.x) {
-    const int r = e / kC, cc = e % kC;
-    smem[cc * lds_len<Q>() + lpad(pos_of_band_row(r, g.b, Q))] = cmul(ph[e], mh[e]);
-  }
-  __syncthreads();
+  int jt, c, t;
+  bool valid;
+  col_coords<Q>(g.nt, jt, c, t, valid);
+  const int k = blockIdx.y, clip = blockIdx.z;
+  cf *buf = smem + (threadIdx.x / T) * lds_len<Q>();
+  const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + jt) * g.B * kC + c;
+  const cf *mh = Mh + (size_t(clip) * g.nt + jt) * g.B * kC + c;
   cf v[E];
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = buf[lpad(t + T * i)];
-  __syncthreads();
+  for (int i = 0; i < E; ++i) {
+    const int r = band_row_of(t + T * i, Q, g.b);
+    v[i] = r >= 0 ? cmul(ph[r * kC], mh[r * kC]) : cmake(0.f, 0.f);
+  }
   fft<Q, +1>(v, buf, t, tw);
+  if (!valid) return;
+  cf *dst = Y + ((size_t(clip) * g.K + k) * g.nt + jt) * size_t(Q) * kC + c;
 #pragma unroll
-  for (int i = 0; i < E; ++i) buf[lpad(t + T * i)] = v[i];
-  __syncthreads();
-  cf *dst = Y + ((size_t(clip) * g.K + k) * g.nt + jt) * size_t(Q) * kC;
-  for (int e = threadIdx.x; e < Q * kC; e += blockDim.x)
-    dst[e] = smem[(e % kC) * lds_len<Q>() + lpad(e / kC)];
+  for (int i = 0; i < E; ++i) dst[(t + T * i) * kC] = v[i];
 }
 
 // Occupancy target of the k-loop row passes: four wavefronts per SIMD (128
@@ -360,28 +369,27 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_adj(cf *__re
 // The chunk sum is accumulated in FP32 in the FFT register layout (band rows
 // only) and stored in FP64; chunks and planes are summed in FP64 later.
 template <int Q>
-__global__ __launch_bounds__(512) void k_pass_y_adj(const cf *__restrict__ V, const cf *__restrict__ bank,
-                                                    double2 *__restrict__ part, Geo g,
-                                                    const cf *__restrict__ tw) {
+__global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *__restrict__ V,
+                                                                    const cf *__restrict__ bank,
+                                                                    double2 *__restrict__ part, Geo g,
+                                                                    const cf *__restrict__ tw) {
   constexpr int T = FftPlan<Q>::T, E = Q / T;
   extern __shared__ cf smem[];
-  const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int jt = blockIdx.x, kc = blockIdx.y, clip = blockIdx.z;
-  cf *buf = smem + c * lds_len<Q>();
+  int jt, c, t;
+  bool valid;
+  col_coords<Q>(g.nt, jt, c, t, valid);
+  const int kc = blockIdx.y, clip = blockIdx.z;
+  cf *buf = smem + (threadIdx.x / T) * lds_len<Q>();
   cf acc[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) acc[i] = cmake(0.f, 0.f);
   const int k0 = kc * g.kper, k1 = min(g.K, k0 + g.kper);
   for (int k = k0; k < k1; ++k) {
-    const cf *src = V + ((size_t(clip) * g.K + k) * g.nt + jt) * size_t(Q) * kC;
-    for (int e = opaque_lane(threadIdx.x); e < Q * kC; e += blockDim.x)
-      smem[(e % kC) * lds_len<Q>() + lpad(e / kC)] = src[e];
-    __syncthreads();
+    const cf *src = V + ((size_t(clip) * g.K + k) * g.nt + jt) * size_t(Q) * kC + c;
     const int tt = opaque_lane(t);
     cf v[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = buf[lpad(tt + T * i)];
-    __syncthreads();
+    for (int i = 0; i < E; ++i) v[i] = src[(tt + T * i) * kC];
     fft<Q, -1>(v, buf, t, tw);
     const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + jt) * g.B * kC + c;
     const int t2 = opaque_lane(t);
@@ -394,6 +402,7 @@ __global__ __launch_bounds__(512) void k_pass_y_adj(const cf *__restrict__ V, co
       }
     }
   }
+  if (!valid) return;
   double2 *dst = part + ((size_t(clip) * g.P * g.KC + size_t(g.p) * g.KC + kc) * g.nt + jt) * size_t(g.B) * kC + c;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
@@ -406,40 +415,37 @@ __global__ __launch_bounds__(512) void k_pass_y_adj(const cf *__restrict__ V, co
 // Acc = sum over (plane, k-chunk) partials in FP64 (fixed order), scaled by 1/N^2,
 // then the inverse column DFT (band rows -> N rows).
 template <int N>
-__global__ __launch_bounds__(512) void k_grad_cols(const double2 *__restrict__ part, int nparts,
-                                                   cf *__restrict__ out, Geo g, const cf *__restrict__ tw) {
+__global__ __launch_bounds__(ColBlock<N>::threads) void k_grad_cols(const double2 *__restrict__ part, int nparts,
+                                                                   cf *__restrict__ out, Geo g,
+                                                                   const cf *__restrict__ tw) {
   constexpr int T = FftPlan<N>::T, E = N / T;
   extern __shared__ cf smem[];
-  const int c = threadIdx.x / T, t = threadIdx.x % T;
-  const int jt = blockIdx.x, clip = blockIdx.y;
-  cf *buf = smem + c * lds_len<N>();
-  for (int e = threadIdx.x; e < kC * N; e += blockDim.x)
-    smem[(e / N) * lds_len<N>() + lpad(e % N)] = cmake(0.f, 0.f);
-  __syncthreads();
-  const int nE = g.B * kC;
+  int jt, c, t;
+  bool valid;
+  col_coords<N>(g.nt, jt, c, t, valid);
+  const int clip = blockIdx.y;
+  cf *buf = smem + (threadIdx.x / T) * lds_len<N>();
+  const size_t nE = size_t(g.B) * kC;
+  const double2 *src = part + (size_t(clip) * nparts * g.nt + jt) * nE + c;
   const double inv = 1.0 / (double(N) * double(N));
-  for (int e = threadIdx.x; e < nE; e += blockDim.x) {
-    double sx = 0.0, sy = 0.0;
-    for (int s = 0; s < nparts; ++s) {
-      const double2 a = part[((size_t(clip) * nparts + s) * g.nt + jt) * size_t(nE) + e];
-      sx += a.x;
-      sy += a.y;
-    }
-    const int r = e / kC, cc = e % kC;
-    smem[cc * lds_len<N>() + lpad(pos_of_band_row(r, g.b, N))] = cmake(float(sx * inv), float(sy * inv));
-  }
-  __syncthreads();
   cf v[E];
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = buf[lpad(t + T * i)];
-  __syncthreads();
+  for (int i = 0; i < E; ++i) {
+    const int r = band_row_of(t + T * i, N, g.b);
+    double sx = 0.0, sy = 0.0;
+    if (r >= 0)
+      for (int s = 0; s < nparts; ++s) {
+        const double2 a = src[size_t(s) * g.nt * nE + r * kC];
+        sx += a.x;
+        sy += a.y;
+      }
+    v[i] = cmake(float(sx * inv), float(sy * inv));
+  }
   fft<N, +1>(v, buf, t, tw);
+  if (!valid) return;
+  cf *dst = out + (size_t(clip) * g.nt + jt) * size_t(N) * kC + c;
 #pragma unroll
-  for (int i = 0; i < E; ++i) buf[lpad(t + T * i)] = v[i];
-  __syncthreads();
-  cf *dst = out + (size_t(clip) * g.nt + jt) * size_t(N) * kC;
-  for (int e = threadIdx.x; e < N * kC; e += blockDim.x)
-    dst[e] = smem[(e % kC) * lds_len<N>() + lpad(e / kC)];
+  for (int i = 0; i < E; ++i) dst[(t + T * i) * kC] = v[i];
 }
 
 // ------------------------------------------------------------ loss reduction
@@ -536,26 +542,35 @@ int rows_inv_real_l(const char *name, const cf *in, int h, int Wp, float *out, c
   });
 }
 
+template <int L>
+constexpr size_t col_lds() {
+  return size_t(dev::ColBlock<L>::threads / FftPlan<L>::T) * lds_len<L>() * sizeof(cf);
+}
+template <int L>
+unsigned col_blocks(int nt) {
+  return unsigned((nt + dev::ColBlock<L>::tiles - 1) / dev::ColBlock<L>::tiles);
+}
+
 template <int L, int DIR>
 int col_fft_l(const char *name, const cf *in, cf *out, int nt, int in_h, int out_h, const cf *tw, float scale,
               int nclips, hipStream_t s) {
-  constexpr int T = FftPlan<L>::T;
   const size_t rin = in_h < 0 ? L : 2 * in_h + 1, rout = out_h < 0 ? L : 2 * out_h + 1;
-  size_t sh = size_t(kC) * lds_len<L>() * sizeof(cf);
-  return launch(name, KPTR(dev::k_col_fft<L, DIR>), dim3(nt, nclips), sh, s, [&] {
-    hipLaunchKernelGGL((dev::k_col_fft<L, DIR>), dim3(nt, nclips), dim3(kC * T), sh, s, in, out, nt, in_h, out_h,
-                       size_t(nt) * rin * kC, size_t(nt) * rout * kC, tw, scale);
+  constexpr size_t sh = col_lds<L>();
+  const dim3 grid(col_blocks<L>(nt), nclips);
+  return launch(name, KPTR(dev::k_col_fft<L, DIR>), grid, sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_col_fft<L, DIR>), grid, dim3(dev::ColBlock<L>::threads), sh, s, in, out, nt, in_h,
+                       out_h, size_t(nt) * rin * kC, size_t(nt) * rout * kC, tw, scale);
   });
 }
 
 template <int Q>
 int pass_y_fwd_q(const cf *bank, const cf *Mh, cf *Y, const PassGeo &pg, const cf *twQ, int nclips,
                  hipStream_t s) {
-  constexpr int T = FftPlan<Q>::T;
   Geo g = to_geo(pg);
-  size_t sh = size_t(kC) * lds_len<Q>() * sizeof(cf);
-  return launch("pass_y_fwd", KPTR(dev::k_pass_y_fwd<Q>), dim3(g.nt, g.K, nclips), sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_pass_y_fwd<Q>, dim3(g.nt, g.K, nclips), dim3(kC * T), sh, s, bank, Mh, Y, g, twQ);
+  constexpr size_t sh = col_lds<Q>();
+  const dim3 grid(col_blocks<Q>(g.nt), g.K, nclips);
+  return launch("pass_y_fwd", KPTR(dev::k_pass_y_fwd<Q>), grid, sh, s, [&] {
+    hipLaunchKernelGGL(dev::k_pass_y_fwd<Q>, grid, dim3(dev::ColBlock<Q>::threads), sh, s, bank, Mh, Y, g, twQ);
   });
 }
 
@@ -598,22 +613,23 @@ int pass_x_adj_q(cf *Y, const float *G, size_t g_clip_stride, const cf *Gband, c
 template <int Q>
 int pass_y_adj_q(const cf *V, const cf *bank, double2 *part, const PassGeo &pg, const cf *twQ, int nclips,
                  hipStream_t s) {
-  constexpr int T = FftPlan<Q>::T;
   Geo g = to_geo(pg);
-  size_t sh = size_t(kC) * lds_len<Q>() * sizeof(cf);
-  return launch("pass_y_adj", KPTR(dev::k_pass_y_adj<Q>), dim3(g.nt, g.KC, nclips), sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_pass_y_adj<Q>, dim3(g.nt, g.KC, nclips), dim3(kC * T), sh, s, V, bank, part, g, twQ);
+  constexpr size_t sh = col_lds<Q>();
+  const dim3 grid(col_blocks<Q>(g.nt), g.KC, nclips);
+  return launch("pass_y_adj", KPTR(dev::k_pass_y_adj<Q>), grid, sh, s, [&] {
+    hipLaunchKernelGGL(dev::k_pass_y_adj<Q>, grid, dim3(dev::ColBlock<Q>::threads), sh, s, V, bank, part, g, twQ);
   });
 }
 
 template <int N>
 int grad_cols_n(const double2 *part, int nparts, cf *tmp, const PassGeo &pg, const cf *twN, int nclips,
                 hipStream_t s) {
-  constexpr int T = FftPlan<N>::T;
   Geo g = to_geo(pg);
-  size_t shc = size_t(kC) * lds_len<N>() * sizeof(cf);
-  return launch("grad_cols", KPTR(dev::k_grad_cols<N>), dim3(g.nt, nclips), shc, s, [&] {
-    hipLaunchKernelGGL(dev::k_grad_cols<N>, dim3(g.nt, nclips), dim3(kC * T), shc, s, part, nparts, tmp, g, twN);
+  constexpr size_t sh = col_lds<N>();
+  const dim3 grid(col_blocks<N>(g.nt), nclips);
+  return launch("grad_cols", KPTR(dev::k_grad_cols<N>), grid, sh, s, [&] {
+    hipLaunchKernelGGL(dev::k_grad_cols<N>, grid, dim3(dev::ColBlock<N>::threads), sh, s, part, nparts, tmp, g,
+                       twN);
   });
 }
 
