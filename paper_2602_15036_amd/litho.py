@@ -244,3 +244,60 @@ def profile_read() -> dict:
         cnt, ms = rest.split(":")
         out[name] = (int(cnt), float(ms))
     return out
+
+
+class Server:
+    """Continuous-batching server over resident banks (litho_serve_*).
+
+    Requests are host arrays; submit() copies them, poll() returns the results.
+    """
+
+    def __init__(self, banks: Sequence[Bank], hbm_budget: int = 16 << 30, max_slots: int = 8,
+                 max_queue: int = 4096):
+        self._banks = list(banks)
+        arr = (C.c_void_p * len(banks))(*[b.handle.value for b in banks])
+        cfg = A.ServeCfg(hbm_budget=int(hbm_budget), max_slots=int(max_slots), max_queue=int(max_queue))
+        h = C.c_void_p()
+        _check(_lib.litho_serve_create(arr, len(banks), C.byref(cfg), C.byref(h)), "litho_serve_create")
+        self._h = h
+
+    def submit(self, bank: int, mask: np.ndarray, K_use: Optional[int] = None, target: Optional[np.ndarray] = None,
+               slope: float = 50.0, threshold: float = 0.3) -> int:
+        """Queue one clip; mode 1 (image + loss + gradient) when a target is given."""
+        b = self._banks[bank]
+        m = np.ascontiguousarray(mask, dtype=np.float32)
+        if m.shape != (b.n, b.n):
+            raise ValueError(f"mask must be [{b.n}, {b.n}]")
+        t = None if target is None else np.ascontiguousarray(target, dtype=np.float32)
+        req = A.Request(bank=bank, K_use=b.K if K_use is None else int(K_use), mode=0 if t is None else 1,
+                        h_mask=m.ctypes.data_as(C.POINTER(C.c_float)),
+                        h_target=None if t is None else t.ctypes.data_as(C.POINTER(C.c_float)),
+                        slope=slope, threshold=threshold)
+        ticket = C.c_uint64()
+        _check(_lib.litho_serve_submit(self._h, C.byref(req), C.byref(ticket)), "litho_serve_submit")
+        return int(ticket.value)
+
+    def poll(self, ticket: int, n: int, n_focus: int, with_grad: bool, timeout_us: int = -1):
+        """None while pending, else dict(image, grad, loss, t_submit_us, t_start_us, t_done_us)."""
+        img = np.empty((n_focus, n, n), dtype=np.float32)
+        grad = np.empty((n, n), dtype=np.float32) if with_grad else None
+        info = A.ResultInfo()
+        rc = _lib.litho_serve_poll(self._h, C.c_uint64(ticket), img.ctypes.data_as(C.POINTER(C.c_float)),
+                                   None if grad is None else grad.ctypes.data_as(C.POINTER(C.c_float)),
+                                   C.byref(info), int(timeout_us))
+        if rc == A.LITHO_PENDING:
+            return None
+        _check(rc, "litho_serve_poll")
+        return {"image": img, "grad": grad, "loss": info.loss if with_grad else None,
+                "t_submit_us": info.t_submit_us, "t_start_us": info.t_start_us, "t_done_us": info.t_done_us}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.litho_serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

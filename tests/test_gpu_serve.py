@@ -1,0 +1,93 @@
+"""Served stream on the GPU: results are the same alone and in a mixed batch,
+match the oracle, and the serve ABI reports its errors."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2602_15036_amd import litho
+    return litho
+
+
+@pytest.fixture(scope="module")
+def banks(L):
+    out = []
+    for n in (256, 512):
+        out.append(L.Bank.from_spec(W.serve_optics(n).with_(K=20)))
+    return out
+
+
+def _requests():
+    reqs = []
+    rng = np.random.default_rng(3000)
+    for i in range(24):
+        bi = int(rng.integers(0, 2))
+        n = (256, 512)[bi]
+        kind = "manhattan" if i % 2 else "curvilinear"
+        m = W.manhattan_mask(n, 50 + i, n_rects=max(1, 20 * n * n // 16384)) if kind == "manhattan" \
+            else W.curvilinear_mask(n, 50 + i)
+        mode = int(rng.integers(0, 2))
+        K = int(rng.integers(12, 21))
+        T = W.manhattan_target(n, 80 + i) if mode else None
+        reqs.append((bi, n, W.as_f32_exact(m), K, T))
+    return reqs
+
+
+def test_alone_equals_mixed_and_matches_oracle(L, banks):
+    reqs = _requests()
+    srv = L.Server(banks, hbm_budget=2 << 30, max_slots=6)
+    # mixed: submit everything, then collect
+    tickets = [srv.submit(bi, m, K_use=K, target=T) for (bi, n, m, K, T) in reqs]
+    mixed = [srv.poll(t, n, 1, T is not None) for t, (bi, n, m, K, T) in zip(tickets, reqs)]
+    # overlap: some request started before another finished
+    spans = sorted((r["t_start_us"], r["t_done_us"]) for r in mixed)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    # alone: one at a time
+    for (bi, n, m, K, T), mix in zip(reqs, mixed):
+        t = srv.submit(bi, m, K_use=K, target=T)
+        alone = srv.poll(t, n, 1, T is not None)
+        assert np.array_equal(alone["image"], mix["image"])
+        if T is not None:
+            assert np.array_equal(alone["grad"], mix["grad"])
+            assert alone["loss"] == mix["loss"]
+    srv.close()
+    # oracle parity on two of them
+    for idx in (0, 1):
+        bi, n, m, K, T = reqs[idx]
+        lam, phi = O.socs_kernels(W.serve_optics(n), 0.0, K=K)
+        ref = O.image(m, lam, phi, method="fft")
+        err = np.linalg.norm(mixed[idx]["image"][0] - ref) / np.linalg.norm(ref)
+        assert err < 1e-5
+
+
+def test_serve_errors(L, banks):
+    srv = L.Server(banks, hbm_budget=1 << 20, max_slots=2, max_queue=2)   # 1 MiB: nothing fits
+    m = np.zeros((256, 256), np.float32)
+    with pytest.raises(L.LithoError) as e:
+        srv.submit(0, m, K_use=8)
+    assert "NOMEM" in str(e.value)
+    srv.close()
+    srv = L.Server(banks, hbm_budget=4 << 30, max_slots=1, max_queue=2)
+    with pytest.raises(L.LithoError):
+        srv.submit(0, m, K_use=99)
+    with pytest.raises(L.LithoError) as e:
+        srv.poll(424242, 256, 1, False, timeout_us=0)
+    assert "NOTFOUND" in str(e.value)
+    tickets = []
+    busy = False
+    for _ in range(8):
+        try:
+            tickets.append(srv.submit(1, np.zeros((512, 512), np.float32), K_use=20))
+        except L.LithoError as err:
+            assert "BUSY" in str(err)
+            busy = True
+    assert busy
+    for t in tickets:
+        assert srv.poll(t, 512, 1, False) is not None
+    srv.close()
