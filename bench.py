@@ -35,6 +35,10 @@ def parse():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-clips", type=int, default=3, help="clips in the oracle sample")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run one device copy of MIB MiB (HBM counter calibration) and exit")
+    ap.add_argument("--serve-requests", type=int, default=768,
+                    help="requests in the served-stream latency sample (0: skip)")
     return ap.parse_args()
 
 
@@ -62,6 +66,30 @@ def kernel_model(name, n, Q, B, K, P, clips):
     return by, fl
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None when the kernel sources have
+    changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_ilt_step_1024x16_K24.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        for tok in line.split():
+            if "=" in tok:
+                k, v = tok.split("=", 1)
+                vals[k] = v
+    csrc = os.path.join(ROOT, "paper_2602_15036_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, n), "rb").read() for n in ("kernels.hip", "fft.hpp"))
+    if hashlib.sha256(src).hexdigest()[:16] != vals.get("kernel_source_sha256_16"):
+        return None
+    v = vals.get(f"{kernel}.hbm_bytes_calibrated")
+    return float(v) if v is not None else None
+
+
 def cpu_baseline(n_clips: int):
     """Oracle (FP64, direct DFT) on the first n_clips clips of the workload."""
     import numpy as np
@@ -87,6 +115,74 @@ def cpu_baseline(n_clips: int):
                       f"FP64 direct-DFT oracle, {dt:.1f} s (host has {os.cpu_count()} CPUs)"}
 
 
+def served_stream(L, n_requests: int, rho: float = 0.8, seed: int = 3000):
+    """Served stream: clip sides log-uniform over {256, 512, 1024, 2048},
+    Manhattan/curvilinear 50/50, forward or forward+gradient 50/50, K uniform in
+    16..32 from resident K_max = 32 banks.  First a closed-loop burst measures
+    the saturated request rate; then Poisson arrivals at rho times that rate
+    give the p50/p99 latency (submit -> device work done)."""
+    import threading
+
+    import numpy as np
+
+    import workloads as W
+    sizes = (256, 512, 1024, 2048)
+    banks = [L.Bank.from_spec(W.serve_optics(n)) for n in sizes]
+    # a small pool of seeded clips per size and kind, reused across requests
+    pool = {}
+    for bi, n in enumerate(sizes):
+        for kind in ("manhattan", "curvilinear"):
+            for j in range(2):
+                spec = W.ServeRequestSpec(n=n, kind=kind, mode=0, K_use=16, arrival_s=0.0, seed=seed + 97 * bi + j)
+                pool[(bi, kind, j)] = W.as_f32_exact(W.request_mask(spec)).astype(np.float32)
+        pool[(bi, "target")] = W.manhattan_target(n, seed + 7 + bi).astype(np.float32)
+    reqs = W.served_stream(n_requests, seed, rate_hz=0.0, sizes=sizes)
+    srv = L.Server(banks, hbm_budget=16 << 30, max_slots=8, max_queue=n_requests + 8)
+
+    def args_of(r, i):
+        bi = sizes.index(r.n)
+        m = pool[(bi, r.kind, i % 2)]
+        return bi, m, r.K_use, (pool[(bi, "target")] if r.mode else None)
+
+    def run(arrivals):
+        t0 = time.perf_counter()
+        tickets = [None] * len(reqs)
+
+        def producer():
+            for i, r in enumerate(reqs):
+                if arrivals is not None:
+                    dt = arrivals[i] - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                bi, m, k, tgt = args_of(r, i)
+                tickets[i] = srv.submit(bi, m, K_use=k, target=tgt)
+        th = threading.Thread(target=producer)
+        th.start()
+        lat, pk = [], 0.0
+        for i, r in enumerate(reqs):
+            while tickets[i] is None:
+                time.sleep(1e-4)
+            res = srv.poll(tickets[i], r.n, 1, bool(r.mode))
+            lat.append((res["t_done_us"] - res["t_submit_us"]) * 1e-3)
+            pk += r.n * r.n * r.K_use
+        th.join()
+        return time.perf_counter() - t0, np.array(lat), pk
+
+    run(None)                                   # warm banks, workspaces, slot buffers
+    wall, _, pk = run(None)                     # closed loop: saturated rate
+    mu = len(reqs) / wall
+    rng = np.random.default_rng(seed + 1)
+    arrivals = np.cumsum(rng.exponential(1.0 / (rho * mu), size=len(reqs)))
+    wall2, lat, pk2 = run(list(arrivals))
+    srv.close()
+    for b in banks:
+        b.close()
+    return {"requests": len(reqs), "sizes": list(sizes), "K_range": [16, 32], "grad_fraction": 0.5,
+            "saturated_req_per_s": mu, "saturated_Mpk_per_s": pk / wall / 1e6,
+            "offered_load": rho, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "open_loop_Mpk_per_s": pk2 / wall2 / 1e6, "precision": "fp32"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -100,6 +196,15 @@ def main():
     from paper_2602_15036_amd import litho as L
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration << 18                  # float32 elements
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
     spec = W.CONFIG2
     batch = args.batch
     bank = L.Bank.from_spec(spec)
@@ -165,8 +270,12 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
     by, fl = kernel_model(dom, n, info.inner_grid, info.B, K, P, batch)
     avg = kern[dom]["avg_ms"] * 1e-3
+    traffic = measured_traffic(dom)
     roof = {"kernel": dom, "bound": "alu", "achieved": fl / avg / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": fl / avg / 1e12 / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": fl / avg / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3, copy-calibrated)",
+            "algorithmic_bytes": by,
+            "nonpacked_fp32_peak": 78.6, "frac_of_nonpacked": fl / avg / 1e12 / 78.6,
             "hbm_view": {"achieved_GBps": by / avg / 1e9, "peak_GBps": HBM_PEAK_GBS,
                          "frac": by / avg / 1e9 / HBM_PEAK_GBS}}
     print(json.dumps({"kernels": kern}), file=sys.stderr, flush=True)
@@ -181,6 +290,8 @@ def main():
         "forward_only": {"value": fwd_value, "unit": UNIT, "ms_per_batch": dtf / args.steps * 1e3},
         "roofline": roof,
     }
+    if args.serve_requests > 0:
+        out["serve"] = served_stream(L, args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_clips)
     print(json.dumps(out), flush=True)
