@@ -19,14 +19,14 @@ named in each docstring.
 """
 from .optics import (band_geometry, source_points, pupil_values, tcc_dense,
                      source_pupil_factor, socs_kernels, pupil_near_ties)
-from .socs import (dft_matrix, mask_spectrum, fields, image, image_at,
+from .socs import (dft_matrix, mask_spectrum, fields, image, image_at, image_window,
                    abbe_image, resist, loss_and_residual, gradient,
                    loss_value, fd_gradient, upsample_check)
 
 __all__ = [
     "band_geometry", "source_points", "pupil_values", "tcc_dense",
     "source_pupil_factor", "socs_kernels", "pupil_near_ties",
-    "dft_matrix", "mask_spectrum", "fields", "image", "image_at", "abbe_image",
+    "dft_matrix", "mask_spectrum", "fields", "image", "image_at", "image_window", "abbe_image",
     "resist", "loss_and_residual", "gradient", "loss_value", "fd_gradient",
     "upsample_check",
 ]

@@ -99,6 +99,23 @@ def image_at(mhat, lam, phi, n, ys, xs):
     return out
 
 
+def image_window(mhat, lam, phi, n, y0, x0, h, w):
+    """SOCS image (Eq. 4) on the window rows y0..y0+h, columns x0..x0+w.
+
+    E_k on the window is Vy^T (Phi_k * Mhat) Vx / n^2 with the synthesis DFT
+    matrices restricted to the window rows and columns.
+    """
+    b = (phi.shape[-1] - 1) // 2
+    k = np.arange(-b, b + 1)
+    Vy = dft_matrix(n, k, +1.0)[:, y0:y0 + h]
+    Vx = dft_matrix(n, k, +1.0)[:, x0:x0 + w]
+    out = np.zeros((h, w))
+    for kk in range(lam.size):
+        E = Vy.T @ (phi[kk] * mhat) @ Vx / (n * n)
+        out += lam[kk] * np.abs(E) ** 2
+    return out
+
+
 def abbe_image(m, spec, focus_nm=0.0, dose=1.0):
     """Brute-force Abbe image: sum over source points of coherent images.
 

@@ -4,7 +4,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblitho.so")
+LIB_PATH = os.environ.get("LITHO_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                            "liblitho.so")
 
 LITHO_OK = 0
 LITHO_PENDING = 1

@@ -412,7 +412,9 @@ void fill_twiddles(float2 *out) {
 // wider ones use block barriers and need the whole block.
 template <int L, int DIR>
 __device__ __forceinline__ void fft(cf (&v)[L / FftPlan<L>::T], cf *buf, int t, const cf *tw) {
-  fft_impl<L, DIR>(v, buf, opaque_lane(t), tw, typename FftPlan<L>::R{});
+  // the mask restores the known range 0 <= t < T after the opaque copy, so
+  // padded LDS addresses of t + T*i fold into immediate offsets
+  fft_impl<L, DIR>(v, buf, opaque_lane(t) & (FftPlan<L>::T - 1), tw, typename FftPlan<L>::R{});
 }
 
 }  // namespace dev

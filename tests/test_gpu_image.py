@@ -142,3 +142,18 @@ def test_inner_grid_validation(L):
             bank.set_inner_grid(bad)
     bank.set_inner_grid(256)
     assert bank.inner_grid == 256
+
+
+def test_full_tile_4096_window(L):
+    # 4096 x 4096, three focus planes, K = 32: the 256 x 256 window at the centre
+    spec = W.CONFIG5
+    bank = L.Bank.from_spec(spec)
+    assert bank.inner_grid == 2560
+    m = W.as_f32_exact(W.curvilinear_mask(4096, 4000))
+    img = L.image(bank, dev(m[None])).cpu().numpy()[0]
+    b = bank.b
+    mh = O.mask_spectrum(m, b, "fft")
+    for p, F in enumerate(spec.focus_nm):
+        lam, phi = O.socs_kernels(spec, F, K=32)
+        ref = O.image_window(mh, lam, phi, 4096, 1920, 1920, 256, 256)
+        assert rel_l2(img[p][1920:2176, 1920:2176], ref) < TOL, p

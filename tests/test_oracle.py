@@ -138,6 +138,16 @@ def test_image_at_matches_full_image():
     assert np.abs(O.image_at(mh, lam, phi, 64, ys, xs) - I[ys, xs]).max() < 1e-13
 
 
+def test_image_window_matches_full_image():
+    lam, phi = O.socs_kernels(DIP64, 30.0, K=12)
+    m = W.curvilinear_mask(64, 17)
+    I = O.image(m, lam, phi)
+    b = (phi.shape[-1] - 1) // 2
+    mh = O.mask_spectrum(m, b)
+    win = O.image_window(mh, lam, phi, 64, 10, 37, 20, 27)
+    assert np.abs(win - I[10:30, 37:64]).max() < 1e-13
+
+
 def test_clear_field_dark_field_and_scaling():
     lam, phi = O.socs_kernels(W.CONFIG1, 0.0, K=8)
     b = (phi.shape[-1] - 1) // 2
