@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mp-steps", type=int, default=10, help="timed steps per split-precision mode (0: skip)")
     ap.add_argument("--cpu-clips", type=int, default=3, help="clips in the oracle sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one device copy of MIB MiB (HBM counter calibration) and exit")
@@ -183,6 +184,42 @@ def served_stream(L, n_requests: int, rho: float = 0.8, seed: int = 3000):
             "mean_ms": float(lat.mean()), "open_loop_Mpk_per_s": pk2 / wall2 / 1e6, "precision": "fp32"}
 
 
+def mixed_precision(L, torch, step, fwd, img, grad, steps, pk, fp32_value, fp32_fwd_value):
+    """Each split-precision mode on the same batch: throughput, speed-up over
+    FP32 and relative L2 error of the image and the gradient against the FP32
+    path (the FP32 path itself is held to 1e-5 of the FP64 oracle by the tests)."""
+    step()
+    torch.cuda.synchronize()
+    img32, grad32 = img.clone(), grad.clone()
+    g2 = torch.empty_like(grad)
+    res = {}
+    for name in ("f16x3", "bf16x3", "f16", "bf16"):
+        code = L.prec_code(name)
+        step(code, g2)
+        torch.cuda.synchronize()
+        e_img = float(torch.linalg.vector_norm((img - img32).double()) / torch.linalg.vector_norm(img32.double()))
+        e_grad = float(torch.linalg.vector_norm((g2 - grad32).double()) / torch.linalg.vector_norm(grad32.double()))
+        L.profile_read()
+        L.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(code, g2)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        L.profile_enable(False)
+        prof = L.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fwd(name)
+        torch.cuda.synchronize()
+        dtf = (time.perf_counter() - t0) / steps
+        res[name] = {"value": pk / dt / 1e6, "ms_per_step": dt * 1e3, "speedup_vs_fp32": pk / dt / 1e6 / fp32_value,
+                     "forward_value": pk / dtf / 1e6, "forward_speedup_vs_fp32": pk / dtf / 1e6 / fp32_fwd_value,
+                     "rel_l2_image_vs_fp32": e_img, "rel_l2_grad_vs_fp32": e_grad,
+                     "kernels_avg_ms": {k: round(v[1] / max(v[0], 1), 5) for k, v in prof.items()}}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -217,15 +254,15 @@ def main():
     grad = torch.empty((batch, n, n), device="cuda")
     loss = torch.empty((batch,), device="cuda", dtype=torch.float64)
 
-    def step():
+    def step(prec=L.A.LITHO_PREC_FP32, g=grad):
         L._check(L._lib.litho_image_grad(
             bank.handle, L._dev_ptr(d_mask, "mask"), batch, K, L._dev_ptr(d_target, "target"),
             L.C.byref(L.A.Resist(slope=50.0, threshold=0.3)), None, L._dev_ptr(img, "image"),
-            L._dev_ptr(loss, "loss", torch.float64), L._dev_ptr(grad, "grad"), L.A.LITHO_PREC_FP32,
+            L._dev_ptr(loss, "loss", torch.float64), L._dev_ptr(g, "grad"), prec,
             L.C.c_void_p(L._stream_handle())), "litho_image_grad")
 
-    def fwd():
-        L.image(bank, d_mask, out=img)
+    def fwd(prec="fp32", out=img):
+        L.image(bank, d_mask, out=out, prec=prec)
 
     for _ in range(args.warmup):
         step()
@@ -290,6 +327,9 @@ def main():
         "forward_only": {"value": fwd_value, "unit": UNIT, "ms_per_batch": dtf / args.steps * 1e3},
         "roofline": roof,
     }
+    if args.mp_steps > 0:
+        out["mixed_precision"] = mixed_precision(L, torch, step, fwd, img, grad, args.mp_steps, pk,
+                                                 value, fwd_value)
     if args.serve_requests > 0:
         out["serve"] = served_stream(L, args.serve_requests)
     if not args.no_cpu_baseline:

@@ -60,8 +60,17 @@ enum {
  * the same and the weights sum to one. */
 enum { LITHO_SRC_ANNULAR = 0, LITHO_SRC_DIPOLE_X = 1 };
 
-/* Arithmetic of the per-kernel transforms.  FP32 is the plain form. */
-enum { LITHO_PREC_FP32 = 0 };
+/* Arithmetic of the band DFT stages (the column transforms between the
+ * cropped pupil band and the inner grid; north of those every pass stays FP32,
+ * and loss and gradient reductions stay FP64).
+ *   FP32:        FFT passes in FP32.
+ *   F16X3/BF16X3: the band transforms as dense DFT-GEMMs on the matrix cores,
+ *                FP16 / BF16 operands split into hi + lo halves, products
+ *                hi*hi + hi*lo + lo*hi, FP32 accumulation.  Near-FP32 (F16X3)
+ *                or ~1e-5 relative (BF16X3) accuracy.
+ *   F16/BF16:    the same GEMMs with one FP16 / BF16 term (hi*hi only);
+ *                ~1e-3 relative accuracy, reported as a reference point. */
+enum { LITHO_PREC_FP32 = 0, LITHO_PREC_F16X3 = 1, LITHO_PREC_BF16X3 = 2, LITHO_PREC_F16 = 3, LITHO_PREC_BF16 = 4 };
 
 /* Optical settings of one bank (Sec. III-A, Eqs. 1-2).  All lengths in nm.
  * The clip of n x n pixels is one period of the transforms.  The pupil is
@@ -208,6 +217,7 @@ typedef struct litho_request {
   const float *h_mask;    /* [n][n] host, copied at submit */
   const float *h_target;  /* [n][n] host (mode 1), copied at submit */
   double slope, threshold; /* resist (mode 1) */
+  int prec;            /* LITHO_PREC_* of the request */
 } litho_request_t;
 
 typedef struct litho_result_info {

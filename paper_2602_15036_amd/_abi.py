@@ -19,6 +19,12 @@ LITHO_E_NOTFOUND = -6
 LITHO_SRC_ANNULAR = 0
 LITHO_SRC_DIPOLE_X = 1
 LITHO_PREC_FP32 = 0
+LITHO_PREC_F16X3 = 1
+LITHO_PREC_BF16X3 = 2
+LITHO_PREC_F16 = 3
+LITHO_PREC_BF16 = 4
+PREC_NAMES = {"fp32": LITHO_PREC_FP32, "f16x3": LITHO_PREC_F16X3, "bf16x3": LITHO_PREC_BF16X3,
+              "f16": LITHO_PREC_F16, "bf16": LITHO_PREC_BF16}
 
 ERROR_NAMES = {
     LITHO_E_INVALID: "LITHO_E_INVALID", LITHO_E_UNSUPPORTED: "LITHO_E_UNSUPPORTED",
@@ -56,7 +62,7 @@ class Request(C.Structure):
     _fields_ = [
         ("bank", C.c_int), ("K_use", C.c_int), ("mode", C.c_int),
         ("h_mask", C.POINTER(C.c_float)), ("h_target", C.POINTER(C.c_float)),
-        ("slope", C.c_double), ("threshold", C.c_double),
+        ("slope", C.c_double), ("threshold", C.c_double), ("prec", C.c_int),
     ]
 
 

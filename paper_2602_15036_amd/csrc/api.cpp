@@ -152,9 +152,12 @@ int set_inner_grid(litho_bank *bk, int q) {
     return LITHO_E_INVALID;
   }
   std::lock_guard<std::mutex> lk(bk->mu);
-  if (bk->d_twQ && bk->d_twQ != bk->d_twN) {
+  if ((bk->d_twQ && bk->d_twQ != bk->d_twN) || bk->d_gemm[0] || bk->d_gemm[1])
     LITHO_HIP_TRY(hipDeviceSynchronize());
-    (void)hipFree(bk->d_twQ);
+  if (bk->d_twQ && bk->d_twQ != bk->d_twN) (void)hipFree(bk->d_twQ);
+  for (void *&t : bk->d_gemm) {
+    if (t) (void)hipFree(t);
+    t = nullptr;
   }
   bk->d_twQ = nullptr;
   bk->Q = q;
@@ -163,6 +166,33 @@ int set_inner_grid(litho_bank *bk, int q) {
     return LITHO_OK;
   }
   return make_twiddles(q, &bk->d_twQ);
+}
+
+// Band DFT-GEMM table of the bank's inner grid, uploaded on first use.
+static int gemm_table(litho_bank *bk, bool bf16, const void **out) {
+  std::lock_guard<std::mutex> lk(bk->mu);
+  void *&t = bk->d_gemm[bf16 ? 1 : 0];
+  if (!t) {
+    std::vector<uint16_t> tab;
+    fill_band_table(bk->Q, bk->host.b, bf16, tab);
+    if (hipMalloc(&t, tab.size() * sizeof(uint16_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      t = nullptr;
+      set_error("litho: cannot allocate the band DFT-GEMM table");
+      return LITHO_E_NOMEM;
+    }
+    LITHO_HIP_TRY(hipMemcpy(t, tab.data(), tab.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  }
+  *out = t;
+  return LITHO_OK;
+}
+
+int check_prec(int prec, const char *who) {
+  if (prec < LITHO_PREC_FP32 || prec > LITHO_PREC_BF16) {
+    set_error("%s: unknown precision mode %d", who, prec);
+    return LITHO_E_INVALID;
+  }
+  return LITHO_OK;
 }
 
 }  // namespace litho
@@ -312,6 +342,8 @@ extern "C" void litho_kernels_free(litho_bank_t *bk) {
   for (auto &kv : bk->ws)
     if (kv.second.base) (void)hipFree(kv.second.base);
   if (bk->d_twQ && bk->d_twQ != bk->d_twN) (void)hipFree(bk->d_twQ);
+  for (void *t : bk->d_gemm)
+    if (t) (void)hipFree(t);
   if (bk->d_twN) (void)hipFree(bk->d_twN);
   if (bk->d_phi) (void)hipFree(bk->d_phi);
   delete bk;
@@ -389,7 +421,7 @@ int acquire_workspace(litho_bank *bk, hipStream_t s, size_t bytes, char **out) {
 // Forward (and optionally adjoint) over one chunk of clips.
 int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, int n, const float *target,
               const float *grad_image, float *image, double *loss, float *grad_mask, bool grad, hipStream_t s,
-              double slope, double thr) {
+              double slope, double thr, int prec, const void *gemm_tab) {
   PassGeo g = L.g;
   g.slope = slope;
   g.thr = thr;
@@ -418,7 +450,10 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
   ep.loss_part = lossp;
   for (int pl = 0; pl < g.P; ++pl) {
     g.p = pl;
-    LITHO_TRY(run_pass_y_fwd(bk->d_phi, Mh, Y, g, twQ, n, s));
+    if (prec == LITHO_PREC_FP32)
+      LITHO_TRY(run_pass_y_fwd(bk->d_phi, Mh, Y, g, twQ, n, s));
+    else
+      LITHO_TRY(run_pass_y_fwd_mfma(bk->d_phi, Mh, Y, g, gemm_tab, prec, n, s));
     if (!resample) {
       LITHO_TRY(run_pass_x_fwd(Y, ep, nullptr, g, twQ, n, s));
     } else {
@@ -471,11 +506,7 @@ static int check_call(const litho_bank *bk, const float *d_mask, int batch, int 
     set_error("%s: K_use=%d outside 1..%d", who, K_use, bk->host.K);
     return LITHO_E_INVALID;
   }
-  if (prec != LITHO_PREC_FP32) {
-    set_error("%s: precision mode %d is not supported", who, prec);
-    return LITHO_E_UNSUPPORTED;
-  }
-  return LITHO_OK;
+  return litho::check_prec(prec, who);
 }
 
 namespace litho {
@@ -484,9 +515,12 @@ namespace litho {
 // so the kernels see dense per-clip arrays.  run_chunk() expects exactly that.
 int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, const float *d_target,
                     const litho_resist_t *resist, const float *d_grad_image, float *d_image, double *d_loss,
-                    float *d_grad_mask, bool grad, hipStream_t s) {
+                    float *d_grad_mask, bool grad, int prec, hipStream_t s) {
   if (batch == 0) return LITHO_OK;
   const bool fused = d_target != nullptr;
+  const void *gemm_tab = nullptr;
+  if (prec != LITHO_PREC_FP32)
+    LITHO_TRY(gemm_table(bk, prec == LITHO_PREC_BF16X3 || prec == LITHO_PREC_BF16, &gemm_tab));
   CallLayout L = plan_call(bk, batch, K_use, grad, fused);
   char *ws = nullptr;
   LITHO_TRY(acquire_workspace(bk, s, L.per_clip * size_t(L.chunk), &ws));
@@ -498,7 +532,7 @@ int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, c
                         d_grad_image ? d_grad_image + size_t(c0) * P * NN : nullptr,
                         d_image ? d_image + size_t(c0) * P * NN : nullptr, d_loss ? d_loss + c0 : nullptr,
                         d_grad_mask ? d_grad_mask + size_t(c0) * NN : nullptr, grad, s,
-                        resist ? resist->slope : 0.0, resist ? resist->threshold : 0.0));
+                        resist ? resist->slope : 0.0, resist ? resist->threshold : 0.0, prec, gemm_tab));
   }
   return LITHO_OK;
 }
@@ -514,7 +548,7 @@ extern "C" int litho_image(const litho_bank_t *bank, const float *d_mask, int ba
     return LITHO_E_INVALID;
   }
   return image_grad_impl(const_cast<litho_bank *>(bank), d_mask, batch, K_use, nullptr, nullptr, nullptr,
-                         d_image, nullptr, nullptr, false, static_cast<hipStream_t>(hip_stream));
+                         d_image, nullptr, nullptr, false, prec, static_cast<hipStream_t>(hip_stream));
 }
 
 extern "C" int litho_image_grad(const litho_bank_t *bank, const float *d_mask, int batch, int K_use,
@@ -543,7 +577,7 @@ extern "C" int litho_image_grad(const litho_bank_t *bank, const float *d_mask, i
     return LITHO_E_INVALID;
   }
   return image_grad_impl(const_cast<litho_bank *>(bank), d_mask, batch, K_use, d_target, resist, d_grad_image,
-                         d_image, d_loss, d_grad_mask, true, static_cast<hipStream_t>(hip_stream));
+                         d_image, d_loss, d_grad_mask, true, prec, static_cast<hipStream_t>(hip_stream));
 }
 
 // ============================================================ tracing ABI

@@ -41,6 +41,9 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
 #include <vector>
 
 namespace litho {
@@ -448,6 +451,122 @@ __global__ __launch_bounds__(ColBlock<N>::threads) void k_grad_cols(const double
   for (int i = 0; i < E; ++i) dst[(t + T * i) * kC] = v[i];
 }
 
+
+// ------------------------------------------------------------ split-precision band DFT-GEMM (MFMA)
+// The forward column pass as a dense complex GEMM on the matrix cores:
+//   Y_k^T[kx][y] = sum_ky X_k^T[kx][ky] W[ky][y],  X_k = Phi'_k * Mh,  W[ky][y] = exp(+2 pi i (ky - b) y / Q)
+// with v_mfma_f32_32x32x16_{f16,bf16} and FP32 accumulation.  SPLIT operands are
+// x = hi + lo (hi = round(x), lo = round(x - hi)) and the product keeps
+// hi*hi + hi*lo + lo*hi.  One wavefront computes a 32 (kx) x 128 (y) tile.
+// Operand layout of the 32x32x16 instruction: lane l holds A[l % 32][8 (l / 32) + j]
+// and B[8 (l / 32) + j][l % 32], j = 0..7; accumulator register i of lane l holds
+// D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+template <typename E>
+struct Mfma;
+template <>
+struct Mfma<_Float16> {
+  using V = h8v;
+  __device__ __forceinline__ static f16v run(V a, V b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<__bf16> {
+  using V = b8v;
+  __device__ __forceinline__ static f16v run(V a, V b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Table of the B operand, one block of 64 lanes x 8 values per (K-step, N-tile,
+// component), components re_hi, re_lo, im_hi, im_lo.
+template <typename E, bool SPLIT>
+__global__ __launch_bounds__(64) void k_pass_y_fwd_mfma(const cf *__restrict__ bank, const cf *__restrict__ Mh,
+                                                       cf *__restrict__ Y, Geo g,
+                                                       const typename Mfma<E>::V *__restrict__ tab, float sin,
+                                                       float sout) {
+  using V = typename Mfma<E>::V;
+  constexpr int NTW = 4;  // N-tiles (32 y each) per wavefront
+  const int l = threadIdx.x, m = l & 31, kg = l >> 5;
+  const int mt = blockIdx.x, nb = blockIdx.y, kc = blockIdx.z;
+  const int k = kc % g.K, clip = kc / g.K;
+  const int kx = 32 * mt + m;
+  const int Q = g.Q, nQt = Q / 32, ksteps = (g.B + 15) / 16;
+  const bool col_ok = kx < g.Bp;
+  const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + (col_ok ? kx >> 2 : 0)) * g.B * kC + (kx & 3);
+  const cf *mh = Mh + (size_t(clip) * g.nt + (col_ok ? kx >> 2 : 0)) * g.B * kC + (kx & 3);
+  f16v acc_r[NTW], acc_i[NTW];
+#pragma unroll
+  for (int n = 0; n < NTW; ++n) {
+    acc_r[n] = f16v{};
+    acc_i[n] = f16v{};
+  }
+  for (int ks = 0; ks < ksteps; ++ks) {
+    V arh, ari, nari, arl, ail, nail;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int ky = 16 * ks + 8 * kg + j;
+      cf x = cmake(0.f, 0.f);
+      if (col_ok && ky < g.B) x = cmul(ph[ky * kC], mh[ky * kC]);
+      const float xr = x.x * sin, xi = x.y * sin;
+      const E hr = E(xr), hi = E(xi);
+      arh[j] = hr;
+      ari[j] = hi;
+      nari[j] = E(-xi);
+      if constexpr (SPLIT) {
+        const E lr = E(xr - float(hr)), li = E(xi - float(hi));
+        arl[j] = lr;
+        ail[j] = li;
+        nail[j] = E(-(xi - float(hi)));
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NTW; ++n) {
+      const int ntile = nb * NTW + n;
+      if (ntile >= nQt) break;
+      const V *tb = tab + (size_t(ks) * nQt + ntile) * 4 * 64 + l;
+      const V brh = tb[0], brl = tb[64], bih = tb[128], bil = tb[192];
+      // Yr += Ar Br - Ai Bi ; Yi += Ar Bi + Ai Br
+      acc_r[n] = Mfma<E>::run(arh, brh, acc_r[n]);
+      acc_r[n] = Mfma<E>::run(nari, bih, acc_r[n]);
+      acc_i[n] = Mfma<E>::run(arh, bih, acc_i[n]);
+      acc_i[n] = Mfma<E>::run(ari, brh, acc_i[n]);
+      if constexpr (SPLIT) {
+        acc_r[n] = Mfma<E>::run(arh, brl, acc_r[n]);
+        acc_r[n] = Mfma<E>::run(arl, brh, acc_r[n]);
+        acc_r[n] = Mfma<E>::run(nari, bil, acc_r[n]);
+        acc_r[n] = Mfma<E>::run(nail, bih, acc_r[n]);
+        acc_i[n] = Mfma<E>::run(arh, bil, acc_i[n]);
+        acc_i[n] = Mfma<E>::run(arl, bih, acc_i[n]);
+        acc_i[n] = Mfma<E>::run(ari, brl, acc_i[n]);
+        acc_i[n] = Mfma<E>::run(ail, brh, acc_i[n]);
+      }
+    }
+  }
+  // D rows 8 (i / 4) + 4 kg + (i % 4) are four consecutive kx = one tile column group
+  cf *yk = Y + (size_t(clip) * g.K + k) * g.nt * size_t(Q) * kC;
+#pragma unroll
+  for (int n = 0; n < NTW; ++n) {
+    if (nb * NTW + n >= nQt) break;
+    const int y = 32 * (nb * NTW + n) + m;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jt = 8 * mt + 2 * q + kg;
+      if (jt < g.nt) {
+        float4 *dst = reinterpret_cast<float4 *>(yk + (size_t(jt) * Q + y) * kC);
+        dst[0] = make_float4(acc_r[n][4 * q] * sout, acc_i[n][4 * q] * sout, acc_r[n][4 * q + 1] * sout,
+                             acc_i[n][4 * q + 1] * sout);
+        dst[1] = make_float4(acc_r[n][4 * q + 2] * sout, acc_i[n][4 * q + 2] * sout, acc_r[n][4 * q + 3] * sout,
+                             acc_i[n][4 * q + 3] * sout);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------ loss reduction
 __global__ __launch_bounds__(256) void k_loss_reduce(const double *__restrict__ part, int n_per_clip,
                                                      double *__restrict__ loss) {
@@ -633,6 +752,58 @@ int grad_cols_n(const double2 *part, int nparts, cf *tmp, const PassGeo &pg, con
   });
 }
 
+
+// ---------------------------------------------------------------- split-precision band GEMM
+
+template <typename E>
+int pass_y_fwd_mfma_e(const cf *bank, const cf *Mh, cf *Y, const PassGeo &pg, const void *tab, bool split,
+                      float sin, int nclips, hipStream_t s) {
+  Geo g = to_geo(pg);
+  using V = typename dev::Mfma<E>::V;
+  if (g.Q % 32 != 0) {
+    set_error("pass_y_fwd_mfma: inner grid %d is not a multiple of 32", g.Q);
+    return LITHO_E_UNSUPPORTED;
+  }
+  const dim3 grid((g.B + 31) / 32, (g.Q / 32 + 3) / 4, unsigned(g.K) * nclips);
+  const float sout = 1.0f / sin;
+  if (split)
+    return launch("pass_y_fwd_mfma", KPTR(dev::k_pass_y_fwd_mfma<E, true>), grid, 0, s, [&] {
+      hipLaunchKernelGGL((dev::k_pass_y_fwd_mfma<E, true>), grid, dim3(64), 0, s, bank, Mh, Y, g,
+                         static_cast<const V *>(tab), sin, sout);
+    });
+  return launch("pass_y_fwd_mfma", KPTR(dev::k_pass_y_fwd_mfma<E, false>), grid, 0, s, [&] {
+    hipLaunchKernelGGL((dev::k_pass_y_fwd_mfma<E, false>), grid, dim3(64), 0, s, bank, Mh, Y, g,
+                       static_cast<const V *>(tab), sin, sout);
+  });
+}
+
+template <typename E>
+void fill_band_table_e(int Q, int b, std::vector<uint16_t> &out) {
+  const int B = 2 * b + 1, ksteps = (B + 15) / 16, nQt = Q / 32;
+  out.assign(size_t(ksteps) * nQt * 4 * 64 * 8, 0);
+  for (int ks = 0; ks < ksteps; ++ks)
+    for (int nt = 0; nt < nQt; ++nt)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 8; ++j) {
+          const int ky = 16 * ks + 8 * (l >> 5) + j, y = 32 * nt + (l & 31);
+          double re = 0, im = 0;
+          if (ky < B) {
+            const long long e = ((long long)(ky - b) * y) % Q;
+            const double a = 2.0 * M_PI * double(e) / double(Q);
+            re = std::cos(a);
+            im = std::sin(a);
+          }
+          const E rh = E(float(re)), ih = E(float(im));
+          const E rl = E(float(re - double(float(rh)))), il = E(float(im - double(float(ih))));
+          const E vals[4] = {rh, rl, ih, il};
+          for (int c = 0; c < 4; ++c) {
+            uint16_t bits;
+            std::memcpy(&bits, &vals[c], 2);
+            out[((((size_t(ks) * nQt + nt) * 4 + c) * 64) + l) * 8 + j] = bits;
+          }
+        }
+}
+
 }  // namespace
 
 #define LITHO_CASE(L, CALL) \
@@ -730,6 +901,24 @@ int run_loss_reduce(const double *part, int n_per_clip, double *loss, int nclips
   return launch("loss_reduce", KPTR(dev::k_loss_reduce), dim3(nclips), 0, s, [&] {
     hipLaunchKernelGGL(dev::k_loss_reduce, dim3(nclips), dim3(256), 0, s, part, n_per_clip, loss);
   });
+}
+
+int run_pass_y_fwd_mfma(const cf2 *bank, const cf2 *Mh, cf2 *Y, const PassGeo &g, const void *tab, int prec,
+                        int nclips, hipStream_t s) {
+  const bool split = prec == LITHO_PREC_F16X3 || prec == LITHO_PREC_BF16X3;
+  const bool bf = prec == LITHO_PREC_BF16X3 || prec == LITHO_PREC_BF16;
+  // |Phi'_k M^| <= 1 (the bank's diagonal sum is the source weight sum, the
+  // mask spectrum is scaled 1/N^2), so FP16 operands are scaled by 2^12: still
+  // far from the FP16 maximum, and the low halves stay normal down to 2^-14.
+  if (bf) return pass_y_fwd_mfma_e<__bf16>((const cf *)bank, (const cf *)Mh, (cf *)Y, g, tab, split, 1.0f, nclips, s);
+  return pass_y_fwd_mfma_e<_Float16>((const cf *)bank, (const cf *)Mh, (cf *)Y, g, tab, split, 4096.0f, nclips, s);
+}
+
+void fill_band_table(int Q, int b, bool bf16, std::vector<uint16_t> &out) {
+  if (bf16)
+    fill_band_table_e<__bf16>(Q, b, out);
+  else
+    fill_band_table_e<_Float16>(Q, b, out);
 }
 
 int twiddle_table(int L, std::vector<float2> &out) {

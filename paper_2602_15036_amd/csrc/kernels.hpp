@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 #include <vector>
 
 #include "common.hpp"
@@ -61,5 +62,11 @@ int run_pass_y_adj(const cf2 *V, const cf2 *bank, double2 *part, const PassGeo &
 int run_grad_cols(const double2 *part, int nparts, cf2 *tmp, const PassGeo &g, const cf2 *twN, int nclips,
                   hipStream_t s);
 int run_loss_reduce(const double *part, int n_per_clip, double *loss, int nclips, hipStream_t s);
+
+// Split-precision band DFT-GEMM form of the forward column pass (matrix cores).
+int run_pass_y_fwd_mfma(const cf2 *bank, const cf2 *Mh, cf2 *Y, const PassGeo &g, const void *tab, int prec,
+                        int nclips, hipStream_t s);
+// B-operand table of that GEMM for inner grid Q and band half-width b (FP16 or BF16 bits).
+void fill_band_table(int Q, int b, bool bf16, std::vector<uint16_t> &out);
 
 }  // namespace litho

@@ -38,6 +38,7 @@ struct litho_bank {
   size_t phi_bytes = 0;
   float2 *d_twN = nullptr;   // exp(-2 pi i e / N)
   float2 *d_twQ = nullptr;   // exp(-2 pi i e / Q)
+  void *d_gemm[2] = {nullptr, nullptr};  // band DFT-GEMM tables for Q (FP16, BF16 bits), built on first use
   std::mutex mu;
   std::map<hipStream_t, litho::Workspace> ws;
 };
@@ -47,5 +48,6 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
 int acquire_workspace(litho_bank *bk, hipStream_t s, size_t bytes, char **out);
 int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, const float *d_target,
                     const litho_resist_t *resist, const float *d_grad_image, float *d_image, double *d_loss,
-                    float *d_grad_mask, bool grad, hipStream_t s);
+                    float *d_grad_mask, bool grad, int prec, hipStream_t s);
+int check_prec(int prec, const char *who);
 }  // namespace litho

@@ -23,7 +23,7 @@ namespace {
 
 struct ServeReq {
   litho_bank *bank = nullptr;
-  int K_use = 0, mode = 0, n = 0, P = 1;
+  int K_use = 0, mode = 0, n = 0, P = 1, prec = LITHO_PREC_FP32;
   double slope = 0, thr = 0;
   std::vector<float> mask, target;
   std::vector<float> image, grad;
@@ -88,10 +88,10 @@ class HipExecutor final : public serve::Executor {
     if (r->mode == 1) {
       litho_resist_t res{r->slope, r->thr};
       rc = image_grad_impl(r->bank, s.d_mask, 1, r->K_use, s.d_target, &res, nullptr, s.d_image, s.d_loss,
-                           s.d_grad, true, s.stream);
+                           s.d_grad, true, r->prec, s.stream);
     } else {
       rc = image_grad_impl(r->bank, s.d_mask, 1, r->K_use, nullptr, nullptr, nullptr, s.d_image, nullptr, nullptr,
-                           false, s.stream);
+                           false, r->prec, s.stream);
     }
     if (rc != LITHO_OK) {
       job.error = last_error();
@@ -254,10 +254,12 @@ extern "C" int litho_serve_submit(litho_server_t *srv, const litho_request_t *re
     set_error("litho_serve_submit: invalid request (K_use=%d mode=%d)", req->K_use, req->mode);
     return LITHO_E_INVALID;
   }
+  LITHO_TRY(check_prec(req->prec, "litho_serve_submit"));
   auto r = std::make_shared<ServeReq>();
   r->bank = bk;
   r->K_use = req->K_use;
   r->mode = req->mode;
+  r->prec = req->prec;
   r->n = bk->host.n;
   r->P = bk->host.n_focus;
   r->slope = req->slope;

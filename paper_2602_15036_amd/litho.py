@@ -145,8 +145,18 @@ def _mask_batch(mask: torch.Tensor, n: int) -> torch.Tensor:
     return mask
 
 
+def prec_code(prec) -> int:
+    """LITHO_PREC_* code of a mode name ("fp32", "f16x3", "bf16x3", "f16", "bf16") or code."""
+    if isinstance(prec, str):
+        try:
+            return A.PREC_NAMES[prec.lower()]
+        except KeyError:
+            raise ValueError(f"unknown precision mode {prec!r}") from None
+    return int(prec)
+
+
 def image(bank: Bank, mask: torch.Tensor, K_use: Optional[int] = None,
-          out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+          out: Optional[torch.Tensor] = None, stream=None, prec="fp32") -> torch.Tensor:
     """SOCS aerial image (Eq. 4): [batch, n_focus, n, n] float32 on the mask's device."""
     mask = _mask_batch(mask, bank.n)
     batch = mask.shape[0]
@@ -154,13 +164,13 @@ def image(bank: Bank, mask: torch.Tensor, K_use: Optional[int] = None,
     if out is None:
         out = torch.empty((batch, bank.n_focus, bank.n, bank.n), device=mask.device, dtype=torch.float32)
     _check(_lib.litho_image(bank.handle, _dev_ptr(mask, "mask"), batch, K_use, _dev_ptr(out, "image"),
-                            A.LITHO_PREC_FP32, C.c_void_p(_stream_handle(stream))), "litho_image")
+                            prec_code(prec), C.c_void_p(_stream_handle(stream))), "litho_image")
     return out
 
 
 def image_grad(bank: Bank, mask: torch.Tensor, target: Optional[torch.Tensor] = None,
                slope: float = 50.0, threshold: float = 0.3, grad_image: Optional[torch.Tensor] = None,
-               K_use: Optional[int] = None, want_image: bool = True, stream=None):
+               K_use: Optional[int] = None, want_image: bool = True, stream=None, prec="fp32"):
     """Image, loss and mask gradient (fused sigmoid-L2 loss) or a VJP with dL/dI.
 
     Returns (image or None, loss [batch] float64 or None, grad [batch, n, n]).
@@ -184,7 +194,7 @@ def image_grad(bank: Bank, mask: torch.Tensor, target: Optional[torch.Tensor] = 
         bank.handle, _dev_ptr(mask, "mask"), batch, K_use, _dev_ptr(target, "target"),
         C.byref(resist) if resist is not None else None, _dev_ptr(grad_image, "grad_image"),
         _dev_ptr(img, "image"), _dev_ptr(loss, "loss", torch.float64), _dev_ptr(grad, "grad"),
-        A.LITHO_PREC_FP32, C.c_void_p(_stream_handle(stream))), "litho_image_grad")
+        prec_code(prec), C.c_void_p(_stream_handle(stream))), "litho_image_grad")
     return img, loss, grad
 
 
@@ -262,7 +272,7 @@ class Server:
         self._h = h
 
     def submit(self, bank: int, mask: np.ndarray, K_use: Optional[int] = None, target: Optional[np.ndarray] = None,
-               slope: float = 50.0, threshold: float = 0.3) -> int:
+               slope: float = 50.0, threshold: float = 0.3, prec="fp32") -> int:
         """Queue one clip; mode 1 (image + loss + gradient) when a target is given."""
         b = self._banks[bank]
         m = np.ascontiguousarray(mask, dtype=np.float32)
@@ -272,7 +282,7 @@ class Server:
         req = A.Request(bank=bank, K_use=b.K if K_use is None else int(K_use), mode=0 if t is None else 1,
                         h_mask=m.ctypes.data_as(C.POINTER(C.c_float)),
                         h_target=None if t is None else t.ctypes.data_as(C.POINTER(C.c_float)),
-                        slope=slope, threshold=threshold)
+                        slope=slope, threshold=threshold, prec=prec_code(prec))
         ticket = C.c_uint64()
         _check(_lib.litho_serve_submit(self._h, C.byref(req), C.byref(ticket)), "litho_serve_submit")
         return int(ticket.value)

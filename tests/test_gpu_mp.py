@@ -1,0 +1,126 @@
+"""Split-precision band DFT-GEMM modes against the FP64 oracle (through the C ABI).
+
+Each mode's relative L2 error of the image and the gradient is printed (run
+with -s to see the table).  The gates are loose bounds for each mode's
+arithmetic, there to catch a broken kernel, not accuracy claims:
+  fp32 / f16x3: FP32-level (hi*hi + hi*lo + lo*hi of 11-bit halves ~ 2^-22),
+  bf16x3:       ~2^-16 per product,
+  f16 / bf16:   one 11-bit / 8-bit term, ~2^-11 / 2^-8 per product.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["fp32", "f16x3", "bf16x3", "f16", "bf16"]
+IMG_GATE = {"fp32": 1e-5, "f16x3": 1e-5, "bf16x3": 2e-4, "f16": 5e-3, "bf16": 4e-2}
+GRAD_GATE = {"fp32": 1e-4, "f16x3": 1e-4, "bf16x3": 1e-3, "f16": 2e-2, "bf16": 2e-1}
+SLOPE, THR = 50.0, 0.3
+
+
+def rel_l2(a, b):
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2602_15036_amd import litho
+    return litho
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _banks(spec, K):
+    return [O.socs_kernels(spec, F, K=K) for F in spec.focus_nm]
+
+
+@pytest.mark.parametrize("n,inner", [(128, 0), (256, 0), (256, 256), (512, 0)])
+def test_mp_image_and_gradient_mid_sizes(L, n, inner):
+    # three focus planes, dipole source; inner grids 96 (n=128), 160, 256, 320
+    spec = W.fd_clip_optics(n).with_(K=12)
+    bank = L.Bank.from_spec(spec)
+    bank.set_inner_grid(inner)
+    m = W.as_f32_exact(W.curvilinear_mask(n, 70 + n))
+    T = W.manhattan_target(n, 71 + n)
+    banks = _banks(spec, 12)
+    Lo, go, imgs = O.gradient(m, T, banks, SLOPE, THR)
+    rows = []
+    for mode in MODES:
+        img, loss, grad = L.image_grad(bank, dev(m[None]), target=dev(T[None]), slope=SLOPE, threshold=THR,
+                                       prec=mode)
+        e_img = max(rel_l2(img.cpu().numpy()[0, p], imgs[p]) for p in range(3))
+        e_grad = rel_l2(grad.cpu().numpy()[0], go)
+        e_loss = abs(loss.item() - Lo) / Lo
+        rows.append((mode, e_img, e_grad, e_loss))
+    for mode, e_img, e_grad, e_loss in rows:
+        print(f"n={n} Q={bank.inner_grid} {mode:7s} image {e_img:.2e} grad {e_grad:.2e} loss {e_loss:.2e}")
+    for mode, e_img, e_grad, _ in rows:
+        assert e_img < IMG_GATE[mode], (mode, e_img)
+        assert e_grad < GRAD_GATE[mode], (mode, e_grad)
+
+
+def test_mp_bench_launch_config(L):
+    # 1024 x 1024, K = 24, batch of 16 (inner grid 640): sampled pixels vs the
+    # oracle and the whole batch vs the FP32 path
+    spec = W.CONFIG2
+    bank = L.Bank.from_spec(spec)
+    masks = np.stack([W.as_f32_exact(W.curvilinear_mask(1024, 1000 + s)) for s in range(16)])
+    d = dev(masks)
+    ref32 = L.image(bank, d).cpu().numpy()
+    lam, phi = O.socs_kernels(spec, 0.0, K=24)
+    rng = np.random.default_rng(5)
+    ys = rng.integers(0, 1024, 64)
+    xs = rng.integers(0, 1024, 64)
+    refs = {i: O.image_at(O.mask_spectrum(masks[i], bank.b, "fft"), lam, phi, 1024, ys, xs) for i in (0, 15)}
+    for mode in MODES[1:]:
+        img = L.image(bank, d, prec=mode).cpu().numpy()
+        e32 = rel_l2(img, ref32)
+        eo = max(rel_l2(img[i, 0][ys, xs], refs[i]) for i in refs)
+        print(f"1024x16 K=24 {mode:7s} vs fp32 {e32:.2e} vs oracle (sampled) {eo:.2e}")
+        assert eo < IMG_GATE[mode], (mode, eo)
+
+
+def test_mp_full_tile_4096_window(L):
+    # 4096 x 4096, three planes, K = 32: image on the central 256 x 256 window
+    # vs the oracle, gradient vs the FP32 path (whole tile and window)
+    spec = W.CONFIG5
+    bank = L.Bank.from_spec(spec)
+    m = W.as_f32_exact(W.curvilinear_mask(4096, 4000))
+    T = W.manhattan_target(4096, 4001)
+    mh = O.mask_spectrum(m, bank.b, "fft")
+    refs = []
+    for F in spec.focus_nm:
+        lam, phi = O.socs_kernels(spec, F, K=32)
+        refs.append(O.image_window(mh, lam, phi, 4096, 1920, 1920, 256, 256))
+    win = (slice(1920, 2176), slice(1920, 2176))
+    out = {}
+    for mode in MODES:
+        img, loss, grad = L.image_grad(bank, dev(m[None]), target=dev(T[None]), slope=SLOPE, threshold=THR,
+                                       prec=mode)
+        out[mode] = (img.cpu().numpy()[0], grad.cpu().numpy()[0], loss.item())
+    g32 = out["fp32"][1]
+    for mode in MODES:
+        img, grad, loss = out[mode]
+        e_img = max(rel_l2(img[p][win], refs[p]) for p in range(3))
+        e_gw = rel_l2(grad[win], g32[win])
+        e_g = rel_l2(grad, g32)
+        print(f"4096 P=3 K=32 {mode:7s} image(window, oracle) {e_img:.2e} "
+              f"grad vs fp32: tile {e_g:.2e} window {e_gw:.2e} loss {abs(loss - out['fp32'][2]) / out['fp32'][2]:.2e}")
+        assert e_img < IMG_GATE[mode], (mode, e_img)
+        assert e_g < GRAD_GATE[mode], (mode, e_g)
+
+
+def test_mp_mode_validation(L):
+    bank = L.Bank.from_spec(W.CONFIG1)
+    m = dev(W.manhattan_mask(128, 1)[None])
+    with pytest.raises(L.LithoError):
+        L.image(bank, m, prec=7)
+    with pytest.raises(ValueError):
+        L.image(bank, m, prec="fp8")
