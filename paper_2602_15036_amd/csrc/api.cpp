@@ -152,8 +152,9 @@ int set_inner_grid(litho_bank *bk, int q) {
     return LITHO_E_INVALID;
   }
   std::lock_guard<std::mutex> lk(bk->mu);
-  if ((bk->d_twQ && bk->d_twQ != bk->d_twN) || bk->d_gemm[0] || bk->d_gemm[1])
-    LITHO_HIP_TRY(hipDeviceSynchronize());
+  bool tables = false;
+  for (void *t : bk->d_gemm) tables = tables || t;
+  if ((bk->d_twQ && bk->d_twQ != bk->d_twN) || tables) LITHO_HIP_TRY(hipDeviceSynchronize());
   if (bk->d_twQ && bk->d_twQ != bk->d_twN) (void)hipFree(bk->d_twQ);
   for (void *&t : bk->d_gemm) {
     if (t) (void)hipFree(t);
@@ -168,13 +169,17 @@ int set_inner_grid(litho_bank *bk, int q) {
   return make_twiddles(q, &bk->d_twQ);
 }
 
-// Band DFT-GEMM table of the bank's inner grid, uploaded on first use.
-static int gemm_table(litho_bank *bk, bool bf16, const void **out) {
+// Band DFT-GEMM table of the bank's inner grid (forward or adjoint column
+// pass), uploaded on first use.
+static int gemm_table(litho_bank *bk, bool adj, bool bf16, const void **out) {
   std::lock_guard<std::mutex> lk(bk->mu);
-  void *&t = bk->d_gemm[bf16 ? 1 : 0];
+  void *&t = bk->d_gemm[(adj ? 2 : 0) + (bf16 ? 1 : 0)];
   if (!t) {
     std::vector<uint16_t> tab;
-    fill_band_table(bk->Q, bk->host.b, bf16, tab);
+    if (adj)
+      fill_adj_table(bk->Q, bk->host.b, bf16, tab);
+    else
+      fill_band_table(bk->Q, bk->host.b, bf16, tab);
     if (hipMalloc(&t, tab.size() * sizeof(uint16_t)) != hipSuccess) {
       (void)hipGetLastError();
       t = nullptr;
@@ -361,7 +366,7 @@ size_t workspace_limit_bytes() {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool fused) {
+CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool fused, int prec) {
   CallLayout L;
   const HostBank &h = bk->host;
   PassGeo &g = L.g;
@@ -372,8 +377,12 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
   g.K = K_use; g.Kbank = h.K; g.P = h.n_focus; g.dose = h.dose;
   // k-chunks of the adjoint column pass: enough blocks to fill the device
   // (~2048), each chunk summing kper kernels in FP32 before the FP64 reduction.
+  // The GEMM form has one workgroup per 32-column block of the band (~1024).
   {
-    const int want = int((2048 + size_t(g.nt) * batch - 1) / (size_t(g.nt) * batch));
+    const bool gemm = prec != LITHO_PREC_FP32;
+    const size_t units = gemm ? size_t(adj_gemm_blocks(g.Bp, g.B)) * batch : size_t(g.nt) * batch;
+    const size_t target = gemm ? 1024 : 2048;
+    const int want = int((target + units - 1) / units);
     const int kc = std::max(1, std::min(K_use, want));
     g.kper = (K_use + kc - 1) / kc;
     g.KC = (K_use + g.kper - 1) / g.kper;
@@ -421,7 +430,7 @@ int acquire_workspace(litho_bank *bk, hipStream_t s, size_t bytes, char **out) {
 // Forward (and optionally adjoint) over one chunk of clips.
 int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, int n, const float *target,
               const float *grad_image, float *image, double *loss, float *grad_mask, bool grad, hipStream_t s,
-              double slope, double thr, int prec, const void *gemm_tab) {
+              double slope, double thr, int prec, const void *gemm_fwd, const void *gemm_adj) {
   PassGeo g = L.g;
   g.slope = slope;
   g.thr = thr;
@@ -453,7 +462,7 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
     if (prec == LITHO_PREC_FP32)
       LITHO_TRY(run_pass_y_fwd(bk->d_phi, Mh, Y, g, twQ, n, s));
     else
-      LITHO_TRY(run_pass_y_fwd_mfma(bk->d_phi, Mh, Y, g, gemm_tab, prec, n, s));
+      LITHO_TRY(run_pass_y_fwd_mfma(bk->d_phi, Mh, Y, g, gemm_fwd, prec, n, s));
     if (!resample) {
       LITHO_TRY(run_pass_x_fwd(Y, ep, nullptr, g, twQ, n, s));
     } else {
@@ -476,7 +485,10 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
                             float(1.0 / (double(g.Q) * double(g.Q))), n, s));
       LITHO_TRY(run_pass_x_adj(Y, nullptr, 0, X1, g, twQ, n, s));
     }
-    LITHO_TRY(run_pass_y_adj(Y, bk->d_phi, part, g, twQ, n, s));
+    if (prec == LITHO_PREC_FP32)
+      LITHO_TRY(run_pass_y_adj(Y, bk->d_phi, part, g, twQ, n, s));
+    else
+      LITHO_TRY(run_pass_y_adj_mfma(Y, bk->d_phi, part, g, gemm_adj, prec, n, s));
   }
   if (grad) {
     LITHO_TRY(run_grad_cols(part, g.P * g.KC, S1, g, twN, n, s));
@@ -518,10 +530,13 @@ int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, c
                     float *d_grad_mask, bool grad, int prec, hipStream_t s) {
   if (batch == 0) return LITHO_OK;
   const bool fused = d_target != nullptr;
-  const void *gemm_tab = nullptr;
-  if (prec != LITHO_PREC_FP32)
-    LITHO_TRY(gemm_table(bk, prec == LITHO_PREC_BF16X3 || prec == LITHO_PREC_BF16, &gemm_tab));
-  CallLayout L = plan_call(bk, batch, K_use, grad, fused);
+  const void *gemm_fwd = nullptr, *gemm_adj = nullptr;
+  if (prec != LITHO_PREC_FP32) {
+    const bool bf = prec == LITHO_PREC_BF16X3 || prec == LITHO_PREC_BF16;
+    LITHO_TRY(gemm_table(bk, false, bf, &gemm_fwd));
+    if (grad) LITHO_TRY(gemm_table(bk, true, bf, &gemm_adj));
+  }
+  CallLayout L = plan_call(bk, batch, K_use, grad, fused, prec);
   char *ws = nullptr;
   LITHO_TRY(acquire_workspace(bk, s, L.per_clip * size_t(L.chunk), &ws));
   const size_t NN = size_t(bk->host.n) * bk->host.n;
@@ -532,7 +547,8 @@ int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, c
                         d_grad_image ? d_grad_image + size_t(c0) * P * NN : nullptr,
                         d_image ? d_image + size_t(c0) * P * NN : nullptr, d_loss ? d_loss + c0 : nullptr,
                         d_grad_mask ? d_grad_mask + size_t(c0) * NN : nullptr, grad, s,
-                        resist ? resist->slope : 0.0, resist ? resist->threshold : 0.0, prec, gemm_tab));
+                        resist ? resist->slope : 0.0, resist ? resist->threshold : 0.0, prec, gemm_fwd,
+                        gemm_adj));
   }
   return LITHO_OK;
 }

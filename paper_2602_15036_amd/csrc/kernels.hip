@@ -44,6 +44,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 namespace litho {
@@ -464,6 +465,7 @@ __global__ __launch_bounds__(ColBlock<N>::threads) void k_grad_cols(const double
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 template <typename E>
 struct Mfma;
@@ -482,87 +484,356 @@ struct Mfma<__bf16> {
   }
 };
 
-// Table of the B operand, one block of 64 lanes x 8 values per (K-step, N-tile,
-// component), components re_hi, re_lo, im_hi, im_lo.
+// N-tiles (32 wide) per wave of the GEMM kernels; the waves per workgroup (NW)
+// are a template parameter, 4 or 5, chosen so that the N extent splits evenly.
+constexpr int kGemmNtw = 2;
+
+// A-operand fragments of one K-step (32 x 16) in LDS, in the instruction's
+// lane order: component c, lane l, value j.  Components: re hi, im hi,
+// -im hi and, when split, re lo, im lo, -im lo.  Each component row has 16
+// spare fragments (128 values) that absorb the stores of threads without an
+// element, so that no store needs a branch.
+constexpr int kStageRow = 80;  // fragments per component row (64 used)
+template <typename E, int NC>
+struct AStage {
+  typename Mfma<E>::V v[2][NC][kStageRow];
+};
+
+// Element e < 512 of the 32 x 16 A block (kx local m, K index kk) -> LDS
+// slot; e in [512, 640) -> a spare slot.
+__device__ __forceinline__ int a_slot(int e, int m, int kk) {
+  return e < 512 ? (m + 32 * (kk >> 3)) * 8 + (kk & 7) : e;
+}
+
 template <typename E, bool SPLIT>
-__global__ __launch_bounds__(64) void k_pass_y_fwd_mfma(const cf *__restrict__ bank, const cf *__restrict__ Mh,
-                                                       cf *__restrict__ Y, Geo g,
-                                                       const typename Mfma<E>::V *__restrict__ tab, float sin,
-                                                       float sout) {
+__device__ __forceinline__ void a_store(E *base, int slot, float xr, float xi) {
+  // base points at component 0 of the stage buffer
+  constexpr int R = 8 * kStageRow;
+  const E hr = E(xr), hi = E(xi);
+  base[slot] = hr;
+  base[R + slot] = hi;
+  base[2 * R + slot] = E(-xi);
+  if constexpr (SPLIT) {
+    const float lr = xr - float(hr), li = xi - float(hi);
+    base[3 * R + slot] = E(lr);
+    base[4 * R + slot] = E(li);
+    base[5 * R + slot] = E(-li);
+  }
+}
+
+// One K-step of the complex product on the matrix cores:
+//   Dr += Ar Br - Ai Bi,  Di += Ar Bi + Ai Br
+// with A from the LDS stage and B (re hi, im hi[, re lo, im lo]) in registers.
+template <typename E, bool SPLIT, int NTW, int NB>
+__device__ __forceinline__ void mfma_step(const typename Mfma<E>::V (&a)[SPLIT ? 6 : 3][kStageRow], int l,
+                                          const typename Mfma<E>::V (&b)[NTW][NB], f16v (&acc_r)[NTW],
+                                          f16v (&acc_i)[NTW]) {
   using V = typename Mfma<E>::V;
-  constexpr int NTW = 4;  // N-tiles (32 y each) per wavefront
-  const int l = threadIdx.x, m = l & 31, kg = l >> 5;
-  const int mt = blockIdx.x, nb = blockIdx.y, kc = blockIdx.z;
-  const int k = kc % g.K, clip = kc / g.K;
-  const int kx = 32 * mt + m;
-  const int Q = g.Q, nQt = Q / 32, ksteps = (g.B + 15) / 16;
-  const bool col_ok = kx < g.Bp;
-  const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + (col_ok ? kx >> 2 : 0)) * g.B * kC + (kx & 3);
-  const cf *mh = Mh + (size_t(clip) * g.nt + (col_ok ? kx >> 2 : 0)) * g.B * kC + (kx & 3);
-  f16v acc_r[NTW], acc_i[NTW];
+  const V arh = a[0][l], ari = a[1][l], nari = a[2][l];
 #pragma unroll
   for (int n = 0; n < NTW; ++n) {
+    acc_r[n] = Mfma<E>::run(arh, b[n][0], acc_r[n]);
+    acc_r[n] = Mfma<E>::run(nari, b[n][1], acc_r[n]);
+    acc_i[n] = Mfma<E>::run(arh, b[n][1], acc_i[n]);
+    acc_i[n] = Mfma<E>::run(ari, b[n][0], acc_i[n]);
+  }
+  if constexpr (SPLIT) {
+    const V arl = a[3][l], ail = a[4][l], nail = a[5][l];
+#pragma unroll
+    for (int n = 0; n < NTW; ++n) {
+      acc_r[n] = Mfma<E>::run(arh, b[n][2], acc_r[n]);
+      acc_r[n] = Mfma<E>::run(arl, b[n][0], acc_r[n]);
+      acc_r[n] = Mfma<E>::run(nari, b[n][3], acc_r[n]);
+      acc_r[n] = Mfma<E>::run(nail, b[n][1], acc_r[n]);
+      acc_i[n] = Mfma<E>::run(arh, b[n][3], acc_i[n]);
+      acc_i[n] = Mfma<E>::run(arl, b[n][1], acc_i[n]);
+      acc_i[n] = Mfma<E>::run(ari, b[n][2], acc_i[n]);
+      acc_i[n] = Mfma<E>::run(ail, b[n][0], acc_i[n]);
+    }
+  }
+}
+
+// The K loop shared by both GEMM kernels.  Software pipeline without register
+// copies (a copy would wait for the load in flight): the loop is unrolled by
+// two, LDS stage P = ks & 1 feeds K-step ks, raw A operands of K-step ks + 1
+// were loaded two K-steps earlier into raw[(ks + 1) & 1], and the B fragments
+// of ks + 1 are loaded into b[(ks + 1) & 1] while ks multiplies.
+//   a_load(ks, R &)             raw A operands of K-step ks (any ks; clamped addresses, no
+//                               arithmetic on the loaded values, which would wait for them)
+//   a_put(stage, const R &, ks) zeroes what lies outside the operand and converts into LDS
+//   b_load(ks, b)          B fragments of K-step ks (any ks; clamped)
+// The stage written after the last K-step is never read.
+template <typename E, bool SPLIT, int NTW, int NB, typename R, typename ALoad, typename APut, typename BLoad>
+__device__ __forceinline__ void gemm_kloop(int ksteps, bool active,
+                                           typename Mfma<E>::V (&st)[2][SPLIT ? 6 : 3][kStageRow],
+                                           int l, ALoad &&a_load, APut &&a_put, BLoad &&b_load,
+                                           f16v (&acc_r)[NTW], f16v (&acc_i)[NTW]) {
+  using V = typename Mfma<E>::V;
+  R raw[2];
+  V b[2][NTW][NB];
+  a_load(0, raw[0]);
+  a_put(0, raw[0], 0);
+  a_load(1, raw[1]);
+  a_load(2, raw[0]);
+  b_load(0, b[0]);
+  __syncthreads();
+  auto step = [&](auto pc, int ks) {
+    constexpr int P = decltype(pc)::value;
+    b_load(ks + 1, b[1 - P]);
+    if (active) mfma_step<E, SPLIT, NTW, NB>(st[P], l, b[P], acc_r, acc_i);
+    a_put(1 - P, raw[1 - P], ks + 1);
+    a_load(ks + 3, raw[1 - P]);
+    __syncthreads();
+  };
+  for (int ks = 0; ks < ksteps; ks += 2) {
+    step(std::integral_constant<int, 0>{}, ks);
+    if (ks + 1 < ksteps) step(std::integral_constant<int, 1>{}, ks + 1);
+  }
+}
+
+// Table of the B operand: one block of 64 lanes x 8 values per (K-step,
+// N-tile, component), components re hi, re lo, im hi, im lo.
+//
+// Workgroup: NW waves share one 32-column A block per K-step (built
+// once in LDS from Phi'_k * M^, FP32 -> hi/lo); each wave multiplies it with
+// kGemmNtw N-tiles of the DFT table, prefetched one K-step ahead.
+template <typename E, bool SPLIT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_pass_y_fwd_mfma(const cf *__restrict__ bank,
+                                                                   const cf *__restrict__ Mh, cf *__restrict__ Y,
+                                                                   Geo g, const typename Mfma<E>::V *__restrict__ tab,
+                                                                   float sin, float sout) {
+  using V = typename Mfma<E>::V;
+  constexpr int NC = SPLIT ? 6 : 3, NB = SPLIT ? 4 : 2, EPT = (512 + 64 * NW - 1) / (64 * NW);
+  __shared__ AStage<E, NC> st;
+  const int tid = threadIdx.x, l = tid & 63, m = l & 31, kg = l >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, scalar
+  const int mt = blockIdx.x, k = blockIdx.z % g.K, clip = blockIdx.z / g.K;
+  const int Q = g.Q, nQt = Q / 32, ksteps = (g.B + 15) / 16;
+  const int nt0 = (blockIdx.y * NW + w) * kGemmNtw;
+  const bool active = nt0 < nQt;
+  // this thread's A elements: e = tid + 64 NW i -> tile 8 mt + e / 64, row (e / 4) % 16, column e % 4;
+  // per element a fixed column pointer and row index, so that a K-step costs one add per load
+  const cf *pa[EPT], *pm[EPT];
+  int kyl[EPT], slot[EPT];
+  bool col_ok[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + 64 * NW * i, jt = 8 * mt + (e >> 6);
+    const size_t col = size_t(min(jt, g.nt - 1)) * g.B * kC + (e & 3);
+    pa[i] = bank + (size_t(g.p) * g.Kbank + k) * g.nt * size_t(g.B) * kC + col;
+    pm[i] = Mh + size_t(clip) * g.nt * size_t(g.B) * kC + col;
+    kyl[i] = (e >> 2) & 15;
+    slot[i] = a_slot(e, 4 * ((e >> 6) & 7) + (e & 3), kyl[i]);
+    col_ok[i] = e < 512 && jt < g.nt;
+  }
+  struct Raw {
+    cf v[2 * EPT];
+  };
+  // Loads in the K loop are unconditional (clamped addresses, zeroed when
+  // stored), so that the compiler can count loads in flight.
+  auto a_load = [&](int ks, Raw &x) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int r = min(16 * ks + kyl[i], g.B - 1) * kC;
+      x.v[2 * i] = pa[i][r];
+      x.v[2 * i + 1] = pm[i][r];
+    }
+  };
+  auto a_put = [&](int buf, const Raw &x, int ks) {
+    E *base = reinterpret_cast<E *>(&st.v[buf][0][0]);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const float s = col_ok[i] && 16 * ks + kyl[i] < g.B ? sin : 0.0f;
+      const cf v = cmul(x.v[2 * i], x.v[2 * i + 1]);
+      a_store<E, SPLIT>(base, slot[i], v.x * s, v.y * s);
+    }
+  };
+  const V *tab_l = tab + l;
+  auto b_load = [&](int ks, V (&b)[kGemmNtw][NB]) {
+#pragma unroll
+    for (int n = 0; n < kGemmNtw; ++n) {
+      const int nt = min(nt0 + n, nQt - 1);
+      const V *tb = tab_l + (min(ks, ksteps - 1) * nQt + nt) * 4 * 64;
+      b[n][0] = tb[0];
+      b[n][1] = tb[128];
+      if constexpr (SPLIT) {
+        b[n][2] = tb[64];
+        b[n][3] = tb[192];
+      }
+    }
+  };
+  f16v acc_r[kGemmNtw], acc_i[kGemmNtw];
+#pragma unroll
+  for (int n = 0; n < kGemmNtw; ++n) {
     acc_r[n] = f16v{};
     acc_i[n] = f16v{};
   }
-  for (int ks = 0; ks < ksteps; ++ks) {
-    V arh, ari, nari, arl, ail, nail;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int ky = 16 * ks + 8 * kg + j;
-      cf x = cmake(0.f, 0.f);
-      if (col_ok && ky < g.B) x = cmul(ph[ky * kC], mh[ky * kC]);
-      const float xr = x.x * sin, xi = x.y * sin;
-      const E hr = E(xr), hi = E(xi);
-      arh[j] = hr;
-      ari[j] = hi;
-      nari[j] = E(-xi);
-      if constexpr (SPLIT) {
-        const E lr = E(xr - float(hr)), li = E(xi - float(hi));
-        arl[j] = lr;
-        ail[j] = li;
-        nail[j] = E(-(xi - float(hi)));
-      }
-    }
-#pragma unroll
-    for (int n = 0; n < NTW; ++n) {
-      const int ntile = nb * NTW + n;
-      if (ntile >= nQt) break;
-      const V *tb = tab + (size_t(ks) * nQt + ntile) * 4 * 64 + l;
-      const V brh = tb[0], brl = tb[64], bih = tb[128], bil = tb[192];
-      // Yr += Ar Br - Ai Bi ; Yi += Ar Bi + Ai Br
-      acc_r[n] = Mfma<E>::run(arh, brh, acc_r[n]);
-      acc_r[n] = Mfma<E>::run(nari, bih, acc_r[n]);
-      acc_i[n] = Mfma<E>::run(arh, bih, acc_i[n]);
-      acc_i[n] = Mfma<E>::run(ari, brh, acc_i[n]);
-      if constexpr (SPLIT) {
-        acc_r[n] = Mfma<E>::run(arh, brl, acc_r[n]);
-        acc_r[n] = Mfma<E>::run(arl, brh, acc_r[n]);
-        acc_r[n] = Mfma<E>::run(nari, bil, acc_r[n]);
-        acc_r[n] = Mfma<E>::run(nail, bih, acc_r[n]);
-        acc_i[n] = Mfma<E>::run(arh, bil, acc_i[n]);
-        acc_i[n] = Mfma<E>::run(arl, bih, acc_i[n]);
-        acc_i[n] = Mfma<E>::run(ari, brl, acc_i[n]);
-        acc_i[n] = Mfma<E>::run(ail, brh, acc_i[n]);
-      }
-    }
-  }
-  // D rows 8 (i / 4) + 4 kg + (i % 4) are four consecutive kx = one tile column group
+  gemm_kloop<E, SPLIT, kGemmNtw, NB, Raw>(ksteps, active, st.v, l, a_load, a_put, b_load, acc_r, acc_i);
+  // accumulator register i of lane l: D row 8 (i / 4) + 4 kg + i % 4 = four consecutive kx of tile 8 mt + 2 (i / 4) + kg
   cf *yk = Y + (size_t(clip) * g.K + k) * g.nt * size_t(Q) * kC;
 #pragma unroll
-  for (int n = 0; n < NTW; ++n) {
-    if (nb * NTW + n >= nQt) break;
-    const int y = 32 * (nb * NTW + n) + m;
+  for (int n = 0; n < kGemmNtw; ++n) {
+    if (nt0 + n >= nQt) break;
+    const int y = 32 * (nt0 + n) + m;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int jt = 8 * mt + 2 * q + kg;
       if (jt < g.nt) {
-        float4 *dst = reinterpret_cast<float4 *>(yk + (size_t(jt) * Q + y) * kC);
-        dst[0] = make_float4(acc_r[n][4 * q] * sout, acc_i[n][4 * q] * sout, acc_r[n][4 * q + 1] * sout,
-                             acc_i[n][4 * q + 1] * sout);
-        dst[1] = make_float4(acc_r[n][4 * q + 2] * sout, acc_i[n][4 * q + 2] * sout, acc_r[n][4 * q + 3] * sout,
-                             acc_i[n][4 * q + 3] * sout);
+        // streaming stores: Y is read back by the next pass, not by this one, and
+        // should not evict the DFT table from L2
+        f4v *dst = reinterpret_cast<f4v *>(yk + (size_t(jt) * Q + y) * kC);
+        const f4v lo = {acc_r[n][4 * q] * sout, acc_i[n][4 * q] * sout, acc_r[n][4 * q + 1] * sout,
+                        acc_i[n][4 * q + 1] * sout};
+        const f4v hi = {acc_r[n][4 * q + 2] * sout, acc_i[n][4 * q + 2] * sout, acc_r[n][4 * q + 3] * sout,
+                        acc_i[n][4 * q + 3] * sout};
+        __builtin_nontemporal_store(lo, dst);
+        __builtin_nontemporal_store(hi, dst + 1);
       }
+    }
+  }
+}
+
+// Adjoint column pass as a GEMM: per kernel k,
+//   U_k^T[kx][ky] = sum_y V_k^T[kx][y] W[y][ky],  W[y][ky] = exp(-2 pi i (ky - b) y / Q),
+// then acc[kx][ky] += conj(Phi'_k[ky][kx]) U_k[ky][kx] over the kernels of the
+// chunk (FP32), stored as the chunk's FP64 partial.  A workgroup owns 32 kx
+// columns and NW 32-row tiles of ky, one per wave, so that with NW = 10 a
+// 317-row band is covered by one workgroup and V_k is read once.  FP16 operands of V_k are
+// scaled per workgroup and kernel by the power of two that puts the block's
+// largest component in [2^13, 2^14).
+template <typename E, bool SPLIT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_pass_y_adj_mfma(const cf *__restrict__ V,
+                                                                   const cf *__restrict__ bank,
+                                                                   double2 *__restrict__ part, Geo g,
+                                                                   const typename Mfma<E>::V *__restrict__ tab) {
+  using Vt = typename Mfma<E>::V;
+  constexpr int NC = SPLIT ? 6 : 3, NB = SPLIT ? 4 : 2, EPT = (512 + 64 * NW - 1) / (64 * NW), NTW = 1;
+  constexpr bool kHalf = __is_same(E, _Float16);
+  __shared__ AStage<E, NC> st;
+  __shared__ float wmax[NW];
+  const int tid = threadIdx.x, l = tid & 63, m = l & 31, kg = l >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, scalar
+  const int mt = blockIdx.x;
+  const int kc = blockIdx.z % g.KC, clip = blockIdx.z / g.KC;
+  const int Q = g.Q, ksteps = Q / 16, nBt = (g.B + 31) / 32;
+  const int nt0 = (blockIdx.y * NW + w) * NTW;
+  const bool active = nt0 < nBt;
+  const size_t kstride = size_t(g.nt) * Q * kC;
+  const cf *vc = V + size_t(clip) * g.K * kstride;
+  // per element: column offset, row in the K-step, LDS slot and whether it lies in the band
+  int colo[EPT], kyl[EPT], slot[EPT];
+  bool col_ok[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + 64 * NW * i, jt = 8 * mt + (e >> 6);
+    colo[i] = min(jt, g.nt - 1) * Q * kC + (e & 3);
+    kyl[i] = (e >> 2) & 15;
+    slot[i] = a_slot(e, 4 * ((e >> 6) & 7) + (e & 3), kyl[i]);
+    col_ok[i] = e < 512 && jt < g.nt;
+  }
+  f16v tot_r[NTW], tot_i[NTW];
+#pragma unroll
+  for (int n = 0; n < NTW; ++n) {
+    tot_r[n] = f16v{};
+    tot_i[n] = f16v{};
+  }
+  const int k0 = kc * g.kper, k1 = min(g.K, k0 + g.kper);
+  for (int k = k0; k < k1; ++k) {
+    const cf *src = vc + k * kstride;
+    struct Raw {
+      cf v[EPT];
+    };
+    // unconditional loads (clamped addresses, zeroed after), as in the forward GEMM
+    auto a_load = [&](int ks, Raw &x) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) x.v[i] = src[colo[i] + (16 * min(ks, ksteps - 1) + kyl[i]) * kC];
+    };
+    float sc = 1.0f;
+    if constexpr (kHalf) {
+      float mx = 0.f;
+#pragma unroll 4
+      for (int ks = 0; ks < ksteps; ++ks) {
+        Raw x;
+        a_load(ks, x);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+          if (col_ok[i]) mx = fmaxf(mx, fmaxf(fabsf(x.v[i].x), fabsf(x.v[i].y)));
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+      if (l == 0) wmax[w] = mx;
+      __syncthreads();
+      mx = wmax[0];
+#pragma unroll
+      for (int i = 1; i < NW; ++i) mx = fmaxf(mx, wmax[i]);
+      int ex = 0;
+      (void)frexpf(mx, &ex);  // mx < 2^ex
+      sc = mx > 0.f ? ldexpf(1.0f, 14 - ex) : 1.0f;
+    }
+    auto a_put = [&](int buf, const Raw &x, int) {
+      E *base = reinterpret_cast<E *>(&st.v[buf][0][0]);
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const float s = col_ok[i] ? sc : 0.0f;
+        a_store<E, SPLIT>(base, slot[i], x.v[i].x * s, x.v[i].y * s);
+      }
+    };
+    auto b_load = [&](int ks, Vt (&b)[NTW][NB]) {
+#pragma unroll
+      for (int n = 0; n < NTW; ++n) {
+        const int nt = min(nt0 + n, nBt - 1);
+        const Vt *tb = tab + l + (min(ks, ksteps - 1) * nBt + nt) * 4 * 64;
+        b[n][0] = tb[0];
+        b[n][1] = tb[128];
+        if constexpr (SPLIT) {
+          b[n][2] = tb[64];
+          b[n][3] = tb[192];
+        }
+      }
+    };
+    f16v acc_r[NTW], acc_i[NTW];
+#pragma unroll
+    for (int n = 0; n < NTW; ++n) {
+      acc_r[n] = f16v{};
+      acc_i[n] = f16v{};
+    }
+    gemm_kloop<E, SPLIT, NTW, NB, Raw>(ksteps, active, st.v, l, a_load, a_put, b_load, acc_r, acc_i);
+    // acc += conj(Phi'_k) U; register i of lane l is (kx = 32 mt + 8 (i / 4) + 4 kg + i % 4, ky)
+    const float inv = 1.0f / sc;
+    const cf *ph = bank + (size_t(g.p) * g.Kbank + k) * g.nt * size_t(g.B) * kC;
+#pragma unroll
+    for (int n = 0; n < NTW; ++n) {
+      const int ky = 32 * (nt0 + n) + m;
+      if (ky >= g.B) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int jt = 8 * mt + 2 * q + kg;
+        if (jt >= g.nt) continue;
+        const float4 *w4 = reinterpret_cast<const float4 *>(ph + (size_t(jt) * g.B + ky) * kC);
+        const float4 wa = w4[0], wb = w4[1];
+        const float wr[4] = {wa.x, wa.z, wb.x, wb.z}, wi[4] = {wa.y, wa.w, wb.y, wb.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int i = 4 * q + c;
+          const float ur = acc_r[n][i] * inv, ui = acc_i[n][i] * inv;
+          tot_r[n][i] += wr[c] * ur + wi[c] * ui;
+          tot_i[n][i] += wr[c] * ui - wi[c] * ur;
+        }
+      }
+    }
+  }
+  double2 *dst = part + ((size_t(clip) * g.P + g.p) * g.KC + kc) * g.nt * size_t(g.B) * kC;
+#pragma unroll
+  for (int n = 0; n < NTW; ++n) {
+    const int ky = 32 * (nt0 + n) + m;
+    if (ky >= g.B) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jt = 8 * mt + 2 * q + kg;
+      if (jt >= g.nt) continue;
+      double2 *d = dst + (size_t(jt) * g.B + ky) * kC;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) d[c] = make_double2(tot_r[n][4 * q + c], tot_i[n][4 * q + c]);
     }
   }
 }
@@ -755,26 +1026,39 @@ int grad_cols_n(const double2 *part, int nparts, cf *tmp, const PassGeo &pg, con
 
 // ---------------------------------------------------------------- split-precision band GEMM
 
+template <typename E, bool SPLIT, int NW>
+int pass_y_fwd_mfma_nw(const cf *bank, const cf *Mh, cf *Y, const Geo &g, const void *tab, float sin, int nclips,
+                       hipStream_t s) {
+  using V = typename dev::Mfma<E>::V;
+  constexpr int per_group = 32 * NW * dev::kGemmNtw;
+  const dim3 grid((g.Bp + 31) / 32, (g.Q + per_group - 1) / per_group, unsigned(g.K) * nclips);
+  const float sout = 1.0f / sin;
+  return launch("pass_y_fwd_mfma", KPTR(dev::k_pass_y_fwd_mfma<E, SPLIT, NW>), grid, 0, s, [&] {
+    hipLaunchKernelGGL((dev::k_pass_y_fwd_mfma<E, SPLIT, NW>), grid, dim3(64 * NW), 0, s, bank, Mh, Y, g,
+                       static_cast<const V *>(tab), sin, sout);
+  });
+}
+
+// Five waves when the 32-wide N-tiles split evenly into groups of ten.
+inline bool five_waves(int tiles) { return tiles > 8 && tiles % 10 == 0; }
+// Waves of the adjoint GEMM workgroup: ten when the 32-row ky tiles come in
+// groups of ten, else four.
+inline int adj_gemm_waves(int B) { return (B + 31) / 32 % 10 == 0 ? 10 : 4; }
+
 template <typename E>
 int pass_y_fwd_mfma_e(const cf *bank, const cf *Mh, cf *Y, const PassGeo &pg, const void *tab, bool split,
                       float sin, int nclips, hipStream_t s) {
   Geo g = to_geo(pg);
-  using V = typename dev::Mfma<E>::V;
   if (g.Q % 32 != 0) {
     set_error("pass_y_fwd_mfma: inner grid %d is not a multiple of 32", g.Q);
     return LITHO_E_UNSUPPORTED;
   }
-  const dim3 grid((g.B + 31) / 32, (g.Q / 32 + 3) / 4, unsigned(g.K) * nclips);
-  const float sout = 1.0f / sin;
+  const bool five = false;
   if (split)
-    return launch("pass_y_fwd_mfma", KPTR(dev::k_pass_y_fwd_mfma<E, true>), grid, 0, s, [&] {
-      hipLaunchKernelGGL((dev::k_pass_y_fwd_mfma<E, true>), grid, dim3(64), 0, s, bank, Mh, Y, g,
-                         static_cast<const V *>(tab), sin, sout);
-    });
-  return launch("pass_y_fwd_mfma", KPTR(dev::k_pass_y_fwd_mfma<E, false>), grid, 0, s, [&] {
-    hipLaunchKernelGGL((dev::k_pass_y_fwd_mfma<E, false>), grid, dim3(64), 0, s, bank, Mh, Y, g,
-                       static_cast<const V *>(tab), sin, sout);
-  });
+    return five ? pass_y_fwd_mfma_nw<E, true, 5>(bank, Mh, Y, g, tab, sin, nclips, s)
+                : pass_y_fwd_mfma_nw<E, true, 4>(bank, Mh, Y, g, tab, sin, nclips, s);
+  return five ? pass_y_fwd_mfma_nw<E, false, 5>(bank, Mh, Y, g, tab, sin, nclips, s)
+              : pass_y_fwd_mfma_nw<E, false, 4>(bank, Mh, Y, g, tab, sin, nclips, s);
 }
 
 template <typename E>
@@ -800,6 +1084,62 @@ void fill_band_table_e(int Q, int b, std::vector<uint16_t> &out) {
             uint16_t bits;
             std::memcpy(&bits, &vals[c], 2);
             out[((((size_t(ks) * nQt + nt) * 4 + c) * 64) + l) * 8 + j] = bits;
+          }
+        }
+}
+
+
+template <typename E, bool SPLIT, int NW>
+int pass_y_adj_mfma_nw(const cf *V, const cf *bank, double2 *part, const Geo &g, const void *tab, int nclips,
+                       hipStream_t s) {
+  using Vt = typename dev::Mfma<E>::V;
+  constexpr int per_group = 32 * NW;
+  const dim3 grid((g.Bp + 31) / 32, (g.B + per_group - 1) / per_group, unsigned(g.KC) * nclips);
+  return launch("pass_y_adj_mfma", KPTR(dev::k_pass_y_adj_mfma<E, SPLIT, NW>), grid, 0, s, [&] {
+    hipLaunchKernelGGL((dev::k_pass_y_adj_mfma<E, SPLIT, NW>), grid, dim3(64 * NW), 0, s, V, bank, part, g,
+                       static_cast<const Vt *>(tab));
+  });
+}
+
+template <typename E>
+int pass_y_adj_mfma_e(const cf *V, const cf *bank, double2 *part, const PassGeo &pg, const void *tab, bool split,
+                      int nclips, hipStream_t s) {
+  Geo g = to_geo(pg);
+  if (g.Q % 16 != 0) {
+    set_error("pass_y_adj_mfma: inner grid %d is not a multiple of 16", g.Q);
+    return LITHO_E_UNSUPPORTED;
+  }
+  const bool ten = adj_gemm_waves(g.B) == 10;
+  if (split)
+    return ten ? pass_y_adj_mfma_nw<E, true, 10>(V, bank, part, g, tab, nclips, s)
+               : pass_y_adj_mfma_nw<E, true, 4>(V, bank, part, g, tab, nclips, s);
+  return ten ? pass_y_adj_mfma_nw<E, false, 10>(V, bank, part, g, tab, nclips, s)
+             : pass_y_adj_mfma_nw<E, false, 4>(V, bank, part, g, tab, nclips, s);
+}
+
+template <typename E>
+void fill_adj_table_e(int Q, int b, std::vector<uint16_t> &out) {
+  const int B = 2 * b + 1, ksteps = Q / 16, nBt = (B + 31) / 32;
+  out.assign(size_t(ksteps) * nBt * 4 * 64 * 8, 0);
+  for (int ks = 0; ks < ksteps; ++ks)
+    for (int nt = 0; nt < nBt; ++nt)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 8; ++j) {
+          const int y = 16 * ks + 8 * (l >> 5) + j, ky = 32 * nt + (l & 31);
+          double re = 0, im = 0;
+          if (ky < B) {
+            const long long e = ((long long)(ky - b) * y) % Q;
+            const double a = -2.0 * M_PI * double(e) / double(Q);
+            re = std::cos(a);
+            im = std::sin(a);
+          }
+          const E rh = E(float(re)), ih = E(float(im));
+          const E rl = E(float(re - double(float(rh)))), il = E(float(im - double(float(ih))));
+          const E vals[4] = {rh, rl, ih, il};
+          for (int c = 0; c < 4; ++c) {
+            uint16_t bits;
+            std::memcpy(&bits, &vals[c], 2);
+            out[((((size_t(ks) * nBt + nt) * 4 + c) * 64) + l) * 8 + j] = bits;
           }
         }
 }
@@ -912,6 +1252,26 @@ int run_pass_y_fwd_mfma(const cf2 *bank, const cf2 *Mh, cf2 *Y, const PassGeo &g
   // far from the FP16 maximum, and the low halves stay normal down to 2^-14.
   if (bf) return pass_y_fwd_mfma_e<__bf16>((const cf *)bank, (const cf *)Mh, (cf *)Y, g, tab, split, 1.0f, nclips, s);
   return pass_y_fwd_mfma_e<_Float16>((const cf *)bank, (const cf *)Mh, (cf *)Y, g, tab, split, 4096.0f, nclips, s);
+}
+
+int run_pass_y_adj_mfma(const cf2 *V, const cf2 *bank, double2 *part, const PassGeo &g, const void *tab, int prec,
+                        int nclips, hipStream_t s) {
+  const bool split = prec == LITHO_PREC_F16X3 || prec == LITHO_PREC_BF16X3;
+  if (prec == LITHO_PREC_BF16X3 || prec == LITHO_PREC_BF16)
+    return pass_y_adj_mfma_e<__bf16>((const cf *)V, (const cf *)bank, part, g, tab, split, nclips, s);
+  return pass_y_adj_mfma_e<_Float16>((const cf *)V, (const cf *)bank, part, g, tab, split, nclips, s);
+}
+
+int adj_gemm_blocks(int Bp, int B) {
+  const int per = 32 * adj_gemm_waves(B);
+  return (Bp + 31) / 32 * ((B + per - 1) / per);
+}
+
+void fill_adj_table(int Q, int b, bool bf16, std::vector<uint16_t> &out) {
+  if (bf16)
+    fill_adj_table_e<__bf16>(Q, b, out);
+  else
+    fill_adj_table_e<_Float16>(Q, b, out);
 }
 
 void fill_band_table(int Q, int b, bool bf16, std::vector<uint16_t> &out) {

@@ -68,5 +68,12 @@ int run_pass_y_fwd_mfma(const cf2 *bank, const cf2 *Mh, cf2 *Y, const PassGeo &g
                         int nclips, hipStream_t s);
 // B-operand table of that GEMM for inner grid Q and band half-width b (FP16 or BF16 bits).
 void fill_band_table(int Q, int b, bool bf16, std::vector<uint16_t> &out);
+// Split-precision GEMM form of the adjoint column pass (g.KC / g.kper chunk the
+// kernels as for run_pass_y_adj), and the B-operand table of its GEMM.
+int run_pass_y_adj_mfma(const cf2 *V, const cf2 *bank, double2 *part, const PassGeo &g, const void *tab, int prec,
+                        int nclips, hipStream_t s);
+void fill_adj_table(int Q, int b, bool bf16, std::vector<uint16_t> &out);
+// Workgroups of that GEMM per clip and kernel chunk.
+int adj_gemm_blocks(int Bp, int B);
 
 }  // namespace litho

@@ -38,13 +38,14 @@ struct litho_bank {
   size_t phi_bytes = 0;
   float2 *d_twN = nullptr;   // exp(-2 pi i e / N)
   float2 *d_twQ = nullptr;   // exp(-2 pi i e / Q)
-  void *d_gemm[2] = {nullptr, nullptr};  // band DFT-GEMM tables for Q (FP16, BF16 bits), built on first use
+  // band DFT-GEMM tables for Q, built on first use: [forward FP16, forward BF16, adjoint FP16, adjoint BF16]
+  void *d_gemm[4] = {nullptr, nullptr, nullptr, nullptr};
   std::mutex mu;
   std::map<hipStream_t, litho::Workspace> ws;
 };
 
 namespace litho {
-CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool fused);
+CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool fused, int prec);
 int acquire_workspace(litho_bank *bk, hipStream_t s, size_t bytes, char **out);
 int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, const float *d_target,
                     const litho_resist_t *resist, const float *d_grad_image, float *d_image, double *d_loss,

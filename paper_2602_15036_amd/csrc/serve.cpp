@@ -209,9 +209,9 @@ using namespace litho;
 
 // Device bytes a request holds while it runs: its buffers and the workspace
 // of one clip of its bank.
-static size_t request_footprint(litho_bank *bk, int K_use, int mode) {
+static size_t request_footprint(litho_bank *bk, int K_use, int mode, int prec) {
   const size_t px = size_t(bk->host.n) * bk->host.n;
-  const CallLayout L = plan_call(bk, 1, K_use, mode == 1, mode == 1);
+  const CallLayout L = plan_call(bk, 1, K_use, mode == 1, mode == 1, prec);
   return px * sizeof(float) * (3 + size_t(bk->host.n_focus)) + L.per_clip;
 }
 
@@ -268,7 +268,7 @@ extern "C" int litho_serve_submit(litho_server_t *srv, const litho_request_t *re
   r->mask.assign(req->h_mask, req->h_mask + px);
   if (req->mode == 1) r->target.assign(req->h_target, req->h_target + px);
   auto job = std::make_shared<serve::Job>();
-  job->footprint = request_footprint(bk, req->K_use, req->mode);
+  job->footprint = request_footprint(bk, req->K_use, req->mode, req->prec);
   job->payload = r;
   const int rc = srv->sched->submit(job, ticket);
   if (rc == LITHO_E_NOMEM)
