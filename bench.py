@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mp-steps", type=int, default=10, help="timed steps per split-precision mode (0: skip)")
-    ap.add_argument("--cpu-clips", type=int, default=3, help="clips in the oracle sample")
+    ap.add_argument("--cpu-clips", type=int, default=10, help="clips in the oracle sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one device copy of MIB MiB (HBM counter calibration) and exit")
     ap.add_argument("--serve-requests", type=int, default=768,
@@ -116,12 +116,14 @@ def cpu_baseline(n_clips: int):
                       f"FP64 direct-DFT oracle, {dt:.1f} s (host has {os.cpu_count()} CPUs)"}
 
 
-def served_stream(L, n_requests: int, rho: float = 0.8, seed: int = 3000):
+def served_stream(L, n_requests: int, rho: float = 0.8, seed: int = 3000, device: bool = False):
     """Served stream: clip sides log-uniform over {256, 512, 1024, 2048},
     Manhattan/curvilinear 50/50, forward or forward+gradient 50/50, K uniform in
     16..32 from resident K_max = 32 banks.  First a closed-loop burst measures
     the saturated request rate; then Poisson arrivals at rho times that rate
-    give the p50/p99 latency (submit -> device work done)."""
+    give the p50/p99 latency (submit -> device work done).  device=False: host
+    arrays in and out (copies included); device=True: inputs resident in HBM
+    and results written to device buffers (no host copies)."""
     import threading
 
     import numpy as np
@@ -139,15 +141,43 @@ def served_stream(L, n_requests: int, rho: float = 0.8, seed: int = 3000):
         pool[(bi, "target")] = W.manhattan_target(n, seed + 7 + bi).astype(np.float32)
     reqs = W.served_stream(n_requests, seed, rate_hz=0.0, sizes=sizes)
     srv = L.Server(banks, hbm_budget=16 << 30, max_slots=8, max_queue=n_requests + 8)
+    if device:
+        import torch
+        dpool = {k: torch.from_numpy(v).cuda() for k, v in pool.items()}
+        outs = []
+        for r in reqs:
+            o = {"image": torch.empty((1, r.n, r.n), device="cuda")}
+            if r.mode:
+                o["grad"] = torch.empty((r.n, r.n), device="cuda")
+                o["loss"] = torch.empty((1,), device="cuda", dtype=torch.float64)
+            outs.append(o)
+        torch.cuda.synchronize()
 
     def args_of(r, i):
         bi = sizes.index(r.n)
         m = pool[(bi, r.kind, i % 2)]
         return bi, m, r.K_use, (pool[(bi, "target")] if r.mode else None)
 
+    def submit(i, r):
+        bi, m, k, tgt = args_of(r, i)
+        if not device:
+            return srv.submit(bi, m, K_use=k, target=tgt)
+        o = outs[i]
+        return srv.submit_device(bi, dpool[(bi, r.kind, i % 2)], o["image"], K_use=k,
+                                 target=dpool[(bi, "target")] if r.mode else None, grad=o.get("grad"),
+                                 loss=o.get("loss"))
+
+    def collect(i, r):
+        if device:
+            return srv.poll_info(tickets_ref[0][i])
+        return srv.poll(tickets_ref[0][i], r.n, 1, bool(r.mode))
+
+    tickets_ref = [None]
+
     def run(arrivals):
         t0 = time.perf_counter()
         tickets = [None] * len(reqs)
+        tickets_ref[0] = tickets
 
         def producer():
             for i, r in enumerate(reqs):
@@ -155,15 +185,14 @@ def served_stream(L, n_requests: int, rho: float = 0.8, seed: int = 3000):
                     dt = arrivals[i] - (time.perf_counter() - t0)
                     if dt > 0:
                         time.sleep(dt)
-                bi, m, k, tgt = args_of(r, i)
-                tickets[i] = srv.submit(bi, m, K_use=k, target=tgt)
+                tickets[i] = submit(i, r)
         th = threading.Thread(target=producer)
         th.start()
         lat, pk = [], 0.0
         for i, r in enumerate(reqs):
             while tickets[i] is None:
                 time.sleep(1e-4)
-            res = srv.poll(tickets[i], r.n, 1, bool(r.mode))
+            res = collect(i, r)
             lat.append((res["t_done_us"] - res["t_submit_us"]) * 1e-3)
             pk += r.n * r.n * r.K_use
         th.join()
@@ -181,7 +210,8 @@ def served_stream(L, n_requests: int, rho: float = 0.8, seed: int = 3000):
     return {"requests": len(reqs), "sizes": list(sizes), "K_range": [16, 32], "grad_fraction": 0.5,
             "saturated_req_per_s": mu, "saturated_Mpk_per_s": pk / wall / 1e6,
             "offered_load": rho, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "open_loop_Mpk_per_s": pk2 / wall2 / 1e6, "precision": "fp32"}
+            "mean_ms": float(lat.mean()), "open_loop_Mpk_per_s": pk2 / wall2 / 1e6, "precision": "fp32",
+            "io": "device-resident" if device else "host arrays (PCIe copies included)"}
 
 
 def mixed_precision(L, torch, step, fwd, img, grad, steps, pk, fp32_value, fp32_fwd_value):
@@ -332,6 +362,7 @@ def main():
                                                  value, fwd_value)
     if args.serve_requests > 0:
         out["serve"] = served_stream(L, args.serve_requests)
+        out["serve_device_io"] = served_stream(L, args.serve_requests, device=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_clips)
     print(json.dumps(out), flush=True)

@@ -218,6 +218,20 @@ typedef struct litho_request {
   const float *h_target;  /* [n][n] host (mode 1), copied at submit */
   double slope, threshold; /* resist (mode 1) */
   int prec;            /* LITHO_PREC_* of the request */
+  /* Device-resident I/O (optional).  When d_mask is not NULL the request reads
+   * d_mask [n][n] (and d_target [n][n] in mode 1) from device memory and
+   * writes d_image [n_focus][n][n] (and d_grad [n][n], plus d_loss [1] if not
+   * NULL, in mode 1) there: h_mask and h_target are ignored, nothing is copied
+   * to or from the host, and litho_serve_poll ignores h_image and h_grad
+   * (info->loss is NaN; the loss is in d_loss).  The inputs must be complete
+   * when litho_serve_submit is called (synchronise the stream that produced
+   * them first); the caller keeps all five buffers alive, and the inputs
+   * unmodified, until litho_serve_poll has returned the request. */
+  const float *d_mask;
+  const float *d_target;
+  float *d_image;
+  float *d_grad;
+  double *d_loss;
 } litho_request_t;
 
 typedef struct litho_result_info {
@@ -234,15 +248,18 @@ typedef struct litho_result_info {
 int litho_serve_create(litho_bank_t *const *banks, int n_banks, const litho_serve_cfg_t *cfg,
                        litho_server_t **out);
 
-/* Queue a request; *ticket receives its id.  The mask/target are copied, so
- * the caller may reuse them at once.  LITHO_E_NOMEM if the request can never
- * fit hbm_budget, LITHO_E_BUSY if the queue is full. */
+/* Queue a request; *ticket receives its id.  Host masks/targets are copied,
+ * so the caller may reuse them at once (device-resident requests: see
+ * litho_request_t).  LITHO_E_NOMEM if the request can never fit hbm_budget,
+ * LITHO_E_BUSY if the queue is full, LITHO_E_INVALID for a malformed request. */
 int litho_serve_submit(litho_server_t *srv, const litho_request_t *req, uint64_t *ticket);
 
 /* Wait up to timeout_us (0 = do not wait, < 0 = forever) for a ticket.
  * Returns LITHO_PENDING while running; on completion copies the image
  * ([n_focus][n][n]) and, for mode 1, the gradient ([n][n]) into the host
- * buffers (either may be NULL), fills *info and releases the ticket. */
+ * buffers (either may be NULL; both are ignored for device-resident requests,
+ * whose results are already in their device buffers), fills *info and releases
+ * the ticket. */
 int litho_serve_poll(litho_server_t *srv, uint64_t ticket, float *h_image, float *h_grad,
                      litho_result_info_t *info, int64_t timeout_us);
 

@@ -63,6 +63,8 @@ class Request(C.Structure):
         ("bank", C.c_int), ("K_use", C.c_int), ("mode", C.c_int),
         ("h_mask", C.POINTER(C.c_float)), ("h_target", C.POINTER(C.c_float)),
         ("slope", C.c_double), ("threshold", C.c_double), ("prec", C.c_int),
+        ("d_mask", C.c_void_p), ("d_target", C.c_void_p), ("d_image", C.c_void_p), ("d_grad", C.c_void_p),
+        ("d_loss", C.c_void_p),
     ]
 
 

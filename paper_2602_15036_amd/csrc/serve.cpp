@@ -5,12 +5,15 @@
 // event, device buffers for one request and pinned host staging.  A request
 // on a slot is: pinned copy of its mask (and target) -> H2D -> SOCS image (and
 // loss + gradient) on the slot's stream -> D2H into pinned memory -> event.
+// A device-resident request skips the copies: it reads and writes the
+// caller's device buffers directly.
 // Slots run concurrently, so requests of different clip sizes and banks
 // overlap on the device; every request keeps the bank's resident kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <vector>
 
@@ -28,6 +31,11 @@ struct ServeReq {
   std::vector<float> mask, target;
   std::vector<float> image, grad;
   double loss = 0;
+  // device-resident I/O (d_mask != nullptr)
+  const float *d_mask = nullptr, *d_target = nullptr;
+  float *d_image = nullptr, *d_grad = nullptr;
+  double *d_loss = nullptr;
+  bool on_device() const { return d_mask != nullptr; }
 };
 
 class HipExecutor final : public serve::Executor {
@@ -72,6 +80,7 @@ class HipExecutor final : public serve::Executor {
   int launch(serve::Job &job, int si) override {
     auto *r = static_cast<ServeReq *>(job.payload.get());
     Slot &s = slots_[size_t(si)];
+    if (r->on_device()) return launch_device(job, *r, s);
     const size_t px = size_t(r->n) * r->n;
     int rc = ensure(s, px, r->P);
     if (rc != LITHO_OK) {
@@ -112,6 +121,27 @@ class HipExecutor final : public serve::Executor {
     return LITHO_OK;
   }
 
+  int launch_device(serve::Job &job, ServeReq &r, Slot &s) {
+    int rc;
+    if (r.mode == 1) {
+      litho_resist_t res{r.slope, r.thr};
+      rc = image_grad_impl(r.bank, r.d_mask, 1, r.K_use, r.d_target, &res, nullptr, r.d_image, r.d_loss, r.d_grad,
+                           true, r.prec, s.stream);
+    } else {
+      rc = image_grad_impl(r.bank, r.d_mask, 1, r.K_use, nullptr, nullptr, nullptr, r.d_image, nullptr, nullptr,
+                           false, r.prec, s.stream);
+    }
+    if (rc != LITHO_OK) {
+      job.error = last_error();
+      return rc;
+    }
+    if (hipEventRecord(s.done, s.stream) != hipSuccess) {
+      job.error = "litho_serve: event record failed";
+      return LITHO_E_HIP;
+    }
+    return LITHO_OK;
+  }
+
   bool ready(int si) override {
     Slot &s = slots_[size_t(si)];
     const hipError_t e = hipEventQuery(s.done);
@@ -127,6 +157,10 @@ class HipExecutor final : public serve::Executor {
       return LITHO_E_HIP;
     }
     auto *r = static_cast<ServeReq *>(job.payload.get());
+    if (r->on_device()) {
+      r->loss = std::numeric_limits<double>::quiet_NaN();
+      return LITHO_OK;
+    }
     const size_t px = size_t(r->n) * r->n;
     r->image.assign(s.h_image, s.h_image + px * r->P);
     if (r->mode == 1) {
@@ -207,12 +241,12 @@ struct litho_server {
 
 using namespace litho;
 
-// Device bytes a request holds while it runs: its buffers and the workspace
-// of one clip of its bank.
-static size_t request_footprint(litho_bank *bk, int K_use, int mode, int prec) {
+// Device bytes a request holds while it runs: the workspace of one clip of
+// its bank, plus the slot's I/O buffers unless its I/O is device-resident.
+static size_t request_footprint(litho_bank *bk, int K_use, int mode, int prec, bool on_device) {
   const size_t px = size_t(bk->host.n) * bk->host.n;
   const CallLayout L = plan_call(bk, 1, K_use, mode == 1, mode == 1, prec);
-  return px * sizeof(float) * (3 + size_t(bk->host.n_focus)) + L.per_clip;
+  return (on_device ? 0 : px * sizeof(float) * (3 + size_t(bk->host.n_focus))) + L.per_clip;
 }
 
 extern "C" int litho_serve_create(litho_bank_t *const *banks, int n_banks, const litho_serve_cfg_t *cfg,
@@ -240,8 +274,13 @@ extern "C" int litho_serve_create(litho_bank_t *const *banks, int n_banks, const
 
 extern "C" int litho_serve_submit(litho_server_t *srv, const litho_request_t *req, uint64_t *ticket) {
   clear_error();
-  if (!srv || !req || !ticket || !req->h_mask) {
+  if (!srv || !req || !ticket || (!req->h_mask && !req->d_mask)) {
     set_error("litho_serve_submit: NULL argument");
+    return LITHO_E_INVALID;
+  }
+  const bool dev = req->d_mask != nullptr;
+  if (dev && (!req->d_image || (req->mode == 1 && (!req->d_target || !req->d_grad)))) {
+    set_error("litho_serve_submit: a device-resident request needs d_image (and d_target, d_grad in mode 1)");
     return LITHO_E_INVALID;
   }
   if (req->bank < 0 || req->bank >= int(srv->banks.size())) {
@@ -250,7 +289,7 @@ extern "C" int litho_serve_submit(litho_server_t *srv, const litho_request_t *re
   }
   litho_bank *bk = srv->banks[size_t(req->bank)];
   if (req->K_use < 1 || req->K_use > bk->host.K || (req->mode != 0 && req->mode != 1) ||
-      (req->mode == 1 && !req->h_target)) {
+      (req->mode == 1 && !dev && !req->h_target)) {
     set_error("litho_serve_submit: invalid request (K_use=%d mode=%d)", req->K_use, req->mode);
     return LITHO_E_INVALID;
   }
@@ -265,10 +304,18 @@ extern "C" int litho_serve_submit(litho_server_t *srv, const litho_request_t *re
   r->slope = req->slope;
   r->thr = req->threshold;
   const size_t px = size_t(r->n) * r->n;
-  r->mask.assign(req->h_mask, req->h_mask + px);
-  if (req->mode == 1) r->target.assign(req->h_target, req->h_target + px);
+  if (dev) {
+    r->d_mask = req->d_mask;
+    r->d_target = req->mode == 1 ? req->d_target : nullptr;
+    r->d_image = req->d_image;
+    r->d_grad = req->mode == 1 ? req->d_grad : nullptr;
+    r->d_loss = req->mode == 1 ? req->d_loss : nullptr;
+  } else {
+    r->mask.assign(req->h_mask, req->h_mask + px);
+    if (req->mode == 1) r->target.assign(req->h_target, req->h_target + px);
+  }
   auto job = std::make_shared<serve::Job>();
-  job->footprint = request_footprint(bk, req->K_use, req->mode, req->prec);
+  job->footprint = request_footprint(bk, req->K_use, req->mode, req->prec, dev);
   job->payload = r;
   const int rc = srv->sched->submit(job, ticket);
   if (rc == LITHO_E_NOMEM)
@@ -308,6 +355,7 @@ extern "C" int litho_serve_poll(litho_server_t *srv, uint64_t ticket, float *h_i
     set_error("litho_serve: request failed: %s", job->error.c_str());
     return job->status;
   }
+  if (r->on_device()) return LITHO_OK;
   if (h_image) std::memcpy(h_image, r->image.data(), r->image.size() * sizeof(float));
   if (h_grad && r->mode == 1) std::memcpy(h_grad, r->grad.data(), r->grad.size() * sizeof(float));
   return LITHO_OK;

@@ -48,6 +48,11 @@ def _dev_ptr(t: Optional[torch.Tensor], what: str, dtype=torch.float32):
     return C.c_void_p(t.data_ptr())
 
 
+def _addr(t: Optional[torch.Tensor], what: str, dtype=torch.float32):
+    p = _dev_ptr(t, what, dtype)
+    return None if p is None else p.value
+
+
 SOURCE_KINDS = {"annular": A.LITHO_SRC_ANNULAR, "dipole_x": A.LITHO_SRC_DIPOLE_X}
 
 
@@ -286,6 +291,41 @@ class Server:
         ticket = C.c_uint64()
         _check(_lib.litho_serve_submit(self._h, C.byref(req), C.byref(ticket)), "litho_serve_submit")
         return int(ticket.value)
+
+    def submit_device(self, bank: int, mask: torch.Tensor, image: torch.Tensor, K_use: Optional[int] = None,
+                      target: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None,
+                      loss: Optional[torch.Tensor] = None, slope: float = 50.0, threshold: float = 0.3,
+                      prec="fp32") -> int:
+        """Queue one clip whose inputs and outputs live in device memory.
+
+        mask [n, n] (and target [n, n]) must be complete on submit; the request
+        writes image [n_focus, n, n] (and grad [n, n], loss [1] float64) in place.
+        Keep every tensor alive and the inputs unchanged until poll() returns it.
+        """
+        b = self._banks[bank]
+        n = b.n
+        if mask.shape != (n, n) or image.shape != (b.n_focus, n, n):
+            raise ValueError(f"mask must be [{n}, {n}] and image [{b.n_focus}, {n}, {n}]")
+        mode = 0 if target is None else 1
+        if mode == 1 and (target.shape != (n, n) or grad is None or grad.shape != (n, n)):
+            raise ValueError("mode 1 needs target and grad of shape [n, n]")
+        req = A.Request(bank=bank, K_use=b.K if K_use is None else int(K_use), mode=mode, h_mask=None, h_target=None,
+                        slope=slope, threshold=threshold, prec=prec_code(prec),
+                        d_mask=_addr(mask, "mask"), d_target=_addr(target, "target"),
+                        d_image=_addr(image, "image"), d_grad=_addr(grad, "grad"),
+                        d_loss=_addr(loss, "loss", torch.float64))
+        ticket = C.c_uint64()
+        _check(_lib.litho_serve_submit(self._h, C.byref(req), C.byref(ticket)), "litho_serve_submit")
+        return int(ticket.value)
+
+    def poll_info(self, ticket: int, timeout_us: int = -1):
+        """For device-resident requests: None while pending, else the timing dict."""
+        info = A.ResultInfo()
+        rc = _lib.litho_serve_poll(self._h, C.c_uint64(ticket), None, None, C.byref(info), int(timeout_us))
+        if rc == A.LITHO_PENDING:
+            return None
+        _check(rc, "litho_serve_poll")
+        return {"t_submit_us": info.t_submit_us, "t_start_us": info.t_start_us, "t_done_us": info.t_done_us}
 
     def poll(self, ticket: int, n: int, n_focus: int, with_grad: bool, timeout_us: int = -1):
         """None while pending, else dict(image, grad, loss, t_submit_us, t_start_us, t_done_us)."""

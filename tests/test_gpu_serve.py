@@ -91,3 +91,43 @@ def test_serve_errors(L, banks):
     for t in tickets:
         assert srv.poll(t, 512, 1, False) is not None
     srv.close()
+
+
+def test_device_resident_requests_match_host_requests(L, banks):
+    # the same requests with device-resident I/O: bit-identical to the host
+    # path, mixed with host requests in flight, and one split-precision request
+    import torch
+    reqs = _requests()[:12]
+    srv = L.Server(banks, hbm_budget=2 << 30, max_slots=6)
+    host = [srv.poll(srv.submit(bi, m, K_use=K, target=T), n, 1, T is not None) for (bi, n, m, K, T) in reqs]
+    dev_bufs, tickets = [], []
+    for i, (bi, n, m, K, T) in enumerate(reqs):
+        d = {"mask": torch.from_numpy(m.astype(np.float32)).cuda(), "image": torch.empty((1, n, n), device="cuda")}
+        if T is not None:
+            d.update(target=torch.from_numpy(T.astype(np.float32)).cuda(),
+                     grad=torch.empty((n, n), device="cuda"),
+                     loss=torch.empty((1,), device="cuda", dtype=torch.float64))
+        torch.cuda.synchronize()
+        dev_bufs.append(d)
+        tickets.append(srv.submit_device(bi, d["mask"], d["image"], K_use=K, target=d.get("target"),
+                                         grad=d.get("grad"), loss=d.get("loss")))
+        if i % 3 == 0:   # host requests in between
+            srv.poll(srv.submit(bi, m, K_use=K, target=T), n, 1, T is not None)
+    for t in tickets:
+        info = srv.poll_info(t)
+        assert info["t_done_us"] >= info["t_start_us"] >= info["t_submit_us"]
+    for d, h, (bi, n, m, K, T) in zip(dev_bufs, host, reqs):
+        assert np.array_equal(d["image"].cpu().numpy(), h["image"])
+        if T is not None:
+            assert np.array_equal(d["grad"].cpu().numpy(), h["grad"])
+            assert d["loss"].item() == h["loss"]
+    # split precision through the served form: same as the direct call
+    bi, n, m, K, T = reqs[0]
+    img = torch.empty((1, n, n), device="cuda")
+    srv.poll_info(srv.submit_device(bi, dev_bufs[0]["mask"], img, K_use=K, prec="f16x3"))
+    ref = L.image(banks[bi], dev_bufs[0]["mask"][None], K_use=K, prec="f16x3")
+    assert torch.equal(img, ref[0])
+    with pytest.raises(L.LithoError):      # device request without an output buffer
+        req = L.A.Request(bank=0, K_use=8, mode=0, d_mask=dev_bufs[0]["mask"].data_ptr())
+        L._check(L._lib.litho_serve_submit(srv._h, L.C.byref(req), L.C.byref(L.C.c_uint64())), "litho_serve_submit")
+    srv.close()
