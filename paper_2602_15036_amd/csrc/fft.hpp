@@ -251,14 +251,14 @@ template <> struct FftPlan<512> { static constexpr int T = 32; using R = Radices
 template <> struct FftPlan<1024> { static constexpr int T = 64; using R = Radices<16, 16, 4>; };
 template <> struct FftPlan<2048> { static constexpr int T = 64; using R = Radices<16, 16, 8>; };
 template <> struct FftPlan<4096> { static constexpr int T = 128; using R = Radices<16, 16, 16>; };
-template <> struct FftPlan<96> { static constexpr int T = 8; using R = Radices<12, 4, 2>; };
-template <> struct FftPlan<160> { static constexpr int T = 8; using R = Radices<10, 4, 4>; };
-template <> struct FftPlan<320> { static constexpr int T = 16; using R = Radices<20, 4, 4>; };
-template <> struct FftPlan<640> { static constexpr int T = 32; using R = Radices<10, 4, 4, 4>; };
-template <> struct FftPlan<768> { static constexpr int T = 32; using R = Radices<12, 8, 8>; };
-template <> struct FftPlan<1280> { static constexpr int T = 64; using R = Radices<20, 4, 4, 4>; };
-template <> struct FftPlan<1536> { static constexpr int T = 64; using R = Radices<12, 8, 8, 2>; };
-template <> struct FftPlan<2560> { static constexpr int T = 64; using R = Radices<10, 8, 8, 4>; };
+template <> struct FftPlan<96> { static constexpr int T = 8; using R = Radices<4, 2, 12>; };
+template <> struct FftPlan<160> { static constexpr int T = 8; using R = Radices<4, 4, 10>; };
+template <> struct FftPlan<320> { static constexpr int T = 16; using R = Radices<4, 4, 20>; };
+template <> struct FftPlan<640> { static constexpr int T = 32; using R = Radices<4, 4, 4, 10>; };
+template <> struct FftPlan<768> { static constexpr int T = 32; using R = Radices<8, 8, 12>; };
+template <> struct FftPlan<1280> { static constexpr int T = 64; using R = Radices<4, 4, 4, 20>; };
+template <> struct FftPlan<1536> { static constexpr int T = 64; using R = Radices<2, 8, 8, 12>; };
+template <> struct FftPlan<2560> { static constexpr int T = 64; using R = Radices<8, 8, 4, 10>; };
 template <> struct FftPlan<3072> { static constexpr int T = 64; using R = Radices<16, 16, 12>; };
 
 // LDS index with one pad slot every 32 complex values, and 4 more slots

@@ -77,11 +77,18 @@ struct Epi {
   double *loss_part;       // [clip][P][nblk]
 };
 
+// Band row of FFT position p in [0, L) for the band |f| <= h (2h < L):
+// p + h for p <= h, p - L + h for p >= L - h.  As the unsigned minimum of
+// p + h and p + h - L it is below 2h + 1 exactly for band positions.
+__device__ __forceinline__ unsigned band_row_u(int p, int L, int h) {
+  const unsigned q = unsigned(p + h);
+  return min(q, q - unsigned(L));
+}
+
+// frequency position pos in [0, L) -> centred band row, or -1 if |f| > h (2h < L)
 __device__ __forceinline__ int band_row_of(int pos, int L, int h) {
-  // frequency position pos in [0, L) -> centred band row, or -1 if |f| > h
-  if (pos <= h) return pos + h;
-  if (pos >= L - h) return pos - L + h;
-  return -1;
+  const unsigned j = band_row_u(pos, L, h);
+  return j < unsigned(2 * h + 1) ? int(j) : -1;
 }
 
 __device__ __forceinline__ int pos_of_band_row(int r, int h, int L) {
@@ -93,10 +100,12 @@ __device__ __forceinline__ int pos_of_band_row(int r, int h, int L) {
 template <int L, int T>
 __device__ __forceinline__ void load_band_row(cf (&v)[L / T], const cf *__restrict__ src, int y, int t, int h) {
   t = opaque_lane(t);
+  const cf *row = src + size_t(y) * kC;
+  const unsigned W = unsigned(2 * h + 1);
 #pragma unroll
   for (int i = 0; i < L / T; ++i) {
-    const int j = band_row_of(t + T * i, L, h);
-    v[i] = j >= 0 ? src[(size_t(j >> 2) * L + y) * kC + (j & 3)] : cmake(0.f, 0.f);
+    const unsigned j = band_row_u(t + T * i, L, h);
+    v[i] = j < W ? row[(j >> 2) * unsigned(L * kC) + (j & 3)] : cmake(0.f, 0.f);
   }
 }
 
@@ -106,12 +115,14 @@ template <int L, int T>
 __device__ __forceinline__ void store_band_row(const cf (&v)[L / T], cf *__restrict__ dst, int y, int t, int h,
                                                int Wp, float scale) {
   t = opaque_lane(t);
+  cf *row = dst + size_t(y) * kC;
+  const unsigned W = unsigned(2 * h + 1);
 #pragma unroll
   for (int i = 0; i < L / T; ++i) {
-    const int j = band_row_of(t + T * i, L, h);
-    if (j >= 0) dst[(size_t(j >> 2) * L + y) * kC + (j & 3)] = cscale(v[i], scale);
+    const unsigned j = band_row_u(t + T * i, L, h);
+    if (j < W) row[(j >> 2) * unsigned(L * kC) + (j & 3)] = cscale(v[i], scale);
   }
-  for (int j = 2 * h + 1 + t; j < Wp; j += T) dst[(size_t(j >> 2) * L + y) * kC + (j & 3)] = cmake(0.f, 0.f);
+  for (unsigned j = W + t; j < unsigned(Wp); j += T) row[(j >> 2) * unsigned(L * kC) + (j & 3)] = cmake(0.f, 0.f);
 }
 
 // Block-wide FP64 sum in fixed order; `red` holds blockDim.x doubles.
