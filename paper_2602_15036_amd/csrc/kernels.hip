@@ -95,15 +95,33 @@ __device__ __forceinline__ int pos_of_band_row(int r, int h, int L) {
   return r - h < 0 ? r - h + L : r - h;
 }
 
+// Pruning.  Register element i of a length-L transform holds positions
+// t + T*i, t < T.  When the band half-width h is at most (L - 1) / 4 (always
+// on an inner grid Q >= 4b + 1), elements lying strictly between the two band
+// edges for every lane are zero on input and unused on output.  Kernels built
+// with PR = true state this at compile time, so the first FFT pass folds the
+// zeros and the last pass drops the outputs nobody reads.
+template <int L>
+__host__ __device__ constexpr bool never_in_band(int i) {
+  constexpr int T = FftPlan<L>::T, H = (L - 1) / 4;
+  return T * i > H && T * i + T - 1 < L - H;
+}
+template <int L>
+inline bool prunable(int h) { return h <= (L - 1) / 4; }
+
 // Band row |f| <= h of row y of a tiled array [tiles][L][kC], read straight
 // into the FFT register layout (thread t holds positions t + T*i).
-template <int L, int T>
+template <int L, int T, bool PR = false>
 __device__ __forceinline__ void load_band_row(cf (&v)[L / T], const cf *__restrict__ src, int y, int t, int h) {
   t = opaque_lane(t);
   const cf *row = src + size_t(y) * kC;
   const unsigned W = unsigned(2 * h + 1);
 #pragma unroll
   for (int i = 0; i < L / T; ++i) {
+    if (PR && never_in_band<L>(i)) {
+      v[i] = cmake(0.f, 0.f);
+      continue;
+    }
     const unsigned j = band_row_u(t + T * i, L, h);
     v[i] = j < W ? row[(j >> 2) * unsigned(L * kC) + (j & 3)] : cmake(0.f, 0.f);
   }
@@ -111,7 +129,7 @@ __device__ __forceinline__ void load_band_row(cf (&v)[L / T], const cf *__restri
 
 // Writes the band |f| <= h of a row held in the FFT register layout (scaled)
 // into row y of a tiled array, and zeros in its Wp - (2h+1) pad columns.
-template <int L, int T>
+template <int L, int T, bool PR = false>
 __device__ __forceinline__ void store_band_row(const cf (&v)[L / T], cf *__restrict__ dst, int y, int t, int h,
                                                int Wp, float scale) {
   t = opaque_lane(t);
@@ -119,6 +137,7 @@ __device__ __forceinline__ void store_band_row(const cf (&v)[L / T], cf *__restr
   const unsigned W = unsigned(2 * h + 1);
 #pragma unroll
   for (int i = 0; i < L / T; ++i) {
+    if (PR && never_in_band<L>(i)) continue;
     const unsigned j = band_row_u(t + T * i, L, h);
     if (j < W) row[(j >> 2) * unsigned(L * kC) + (j & 3)] = cscale(v[i], scale);
   }
@@ -264,7 +283,7 @@ __global__ __launch_bounds__(ColBlock<L>::threads) void k_col_fft(const cf *__re
 
 // ------------------------------------------------------------ forward column pass
 // Y_k[jt][y][c] = sum_ky Phi'_k(ky, j) Mh(ky, j) exp(+2 pi i ky y / Q).
-template <int Q>
+template <int Q, bool PR>
 __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_fwd(const cf *__restrict__ bank,
                                                                     const cf *__restrict__ Mh, cf *__restrict__ Y,
                                                                     Geo g, const cf *__restrict__ tw) {
@@ -280,6 +299,10 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_fwd(const cf *_
   cf v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
+    if (PR && never_in_band<Q>(i)) {
+      v[i] = cmake(0.f, 0.f);
+      continue;
+    }
     const int r = band_row_of(t + T * i, Q, g.b);
     v[i] = r >= 0 ? cmul(ph[r * kC], mh[r * kC]) : cmake(0.f, 0.f);
   }
@@ -301,7 +324,7 @@ struct RowWaves {
 // I_Q(y, x) = dose * sum_k |sum_kx Y_k(y, kx) exp(+2 pi i kx x / Q)|^2.
 // OUT 0 (Q == N): image / resist epilogue.  OUT 1 (Q < N): forward row DFT of
 // the I_Q row, keep |gx| <= 2b, scale dose/Q^2, store tiled [ntD][Q][kC] in Ib.
-template <int Q, int OUT>
+template <int Q, int OUT, bool PR>
 __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf *__restrict__ Y, Epi ep, cf *__restrict__ Ib, Geo g,
                                                     const cf *__restrict__ tw) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
@@ -316,7 +339,7 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf
   const cf *yc = Y + size_t(clip) * g.K * kstride;
   for (int k = 0; k < g.K; ++k) {
     cf v[E];
-    load_band_row<Q, T>(v, yc + k * kstride, y, t, g.b);
+    load_band_row<Q, T, PR>(v, yc + k * kstride, y, t, g.b);
     fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) acc[i] += cabs2(v[i]);
@@ -345,7 +368,7 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf
 // wavefront, which reads it completely before writing it).
 // GIN 0: G is a real [Q][Q] array per clip (Q == N), rows strided by Q.
 // GIN 1: G is a band [ntD][Q][kC] (|gx| <= 2b) per clip; its row is synthesised.
-template <int Q, int GIN>
+template <int Q, int GIN, bool PR>
 __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Greal,
                                                     size_t g_clip_stride, const cf *__restrict__ Gband, Geo g,
                                                     const cf *__restrict__ tw) {
@@ -370,12 +393,12 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_adj(cf *__re
   cf *yc = Y + size_t(clip) * g.K * kstride;
   for (int k = 0; k < g.K; ++k) {
     cf v[E];
-    load_band_row<Q, T>(v, yc + k * kstride, y, t, g.b);
+    load_band_row<Q, T, PR>(v, yc + k * kstride, y, t, g.b);
     fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = cscale(v[i], gr[i]);
     fft<Q, -1>(v, xch, t, tw);
-    store_band_row<Q, T>(v, yc + k * kstride, y, t, g.b, g.Bp, 1.0f);
+    store_band_row<Q, T, PR>(v, yc + k * kstride, y, t, g.b, g.Bp, 1.0f);
   }
 }
 
@@ -383,7 +406,7 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_adj(cf *__re
 // part[clip][p*KC + kc][jt][ky][c] = sum_{k in chunk} conj(Phi'_k) * sum_y V_k(y, j) exp(-2 pi i ky y / Q)
 // The chunk sum is accumulated in FP32 in the FFT register layout (band rows
 // only) and stored in FP64; chunks and planes are summed in FP64 later.
-template <int Q>
+template <int Q, bool PR>
 __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *__restrict__ V,
                                                                     const cf *__restrict__ bank,
                                                                     double2 *__restrict__ part, Geo g,
@@ -410,6 +433,7 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *_
     const int t2 = opaque_lane(t);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
+      if (PR && never_in_band<Q>(i)) continue;
       const int r = band_row_of(t2 + T * i, Q, g.b);
       if (r >= 0) {
         const cf w = ph[r * kC];
@@ -421,6 +445,7 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *_
   double2 *dst = part + ((size_t(clip) * g.P * g.KC + size_t(g.p) * g.KC + kc) * g.nt + jt) * size_t(g.B) * kC + c;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
+    if (PR && never_in_band<Q>(i)) continue;
     const int r = band_row_of(t + T * i, Q, g.b);
     if (r >= 0) dst[r * kC] = make_double2(acc[i].x, acc[i].y);
   }
@@ -970,8 +995,14 @@ int pass_y_fwd_q(const cf *bank, const cf *Mh, cf *Y, const PassGeo &pg, const c
   Geo g = to_geo(pg);
   constexpr size_t sh = col_lds<Q>();
   const dim3 grid(col_blocks<Q>(g.nt), g.K, nclips);
-  return launch("pass_y_fwd", KPTR(dev::k_pass_y_fwd<Q>), grid, sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_pass_y_fwd<Q>, grid, dim3(dev::ColBlock<Q>::threads), sh, s, bank, Mh, Y, g, twQ);
+  if (dev::prunable<Q>(g.b))
+    return launch("pass_y_fwd", KPTR(dev::k_pass_y_fwd<Q, true>), grid, sh, s, [&] {
+      hipLaunchKernelGGL((dev::k_pass_y_fwd<Q, true>), grid, dim3(dev::ColBlock<Q>::threads), sh, s, bank, Mh, Y, g,
+                         twQ);
+    });
+  return launch("pass_y_fwd", KPTR(dev::k_pass_y_fwd<Q, false>), grid, sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_pass_y_fwd<Q, false>), grid, dim3(dev::ColBlock<Q>::threads), sh, s, bank, Mh, Y, g,
+                       twQ);
   });
 }
 
@@ -984,13 +1015,19 @@ int pass_x_fwd_q(const cf *Y, const EpiPtrs &ep, cf *Ib, const PassGeo &pg, cons
   const bool band = g.Q != g.N;
   size_t sh = size_t(RPB) * lds_len<Q>() * sizeof(cf);
   sh = std::max(sh, size_t(256) * sizeof(double));
-  if (!band)
-    return launch("pass_x_fwd", KPTR(dev::k_pass_x_fwd<Q, 0>), dim3(Q / RPB, nclips), sh, s, [&] {
-      hipLaunchKernelGGL((dev::k_pass_x_fwd<Q, 0>), dim3(Q / RPB, nclips), dim3(256), sh, s, Y, e, Ib, g, twQ);
-    });
-  return launch("pass_x_fwd", KPTR(dev::k_pass_x_fwd<Q, 1>), dim3(Q / RPB, nclips), sh, s, [&] {
-    hipLaunchKernelGGL((dev::k_pass_x_fwd<Q, 1>), dim3(Q / RPB, nclips), dim3(256), sh, s, Y, e, Ib, g, twQ);
-  });
+  const bool pr = dev::prunable<Q>(g.b);
+  const dim3 grid(Q / RPB, nclips);
+#define LITHO_PX_FWD(OUT, PR)                                                                              \
+  return launch("pass_x_fwd", KPTR(dev::k_pass_x_fwd<Q, OUT, PR>), grid, sh, s, [&] {                       \
+    hipLaunchKernelGGL((dev::k_pass_x_fwd<Q, OUT, PR>), grid, dim3(256), sh, s, Y, e, Ib, g, twQ);          \
+  })
+  if (!band) {
+    if (pr) LITHO_PX_FWD(0, true);
+    LITHO_PX_FWD(0, false);
+  }
+  if (pr) LITHO_PX_FWD(1, true);
+  LITHO_PX_FWD(1, false);
+#undef LITHO_PX_FWD
 }
 
 template <int Q>
@@ -1000,15 +1037,20 @@ int pass_x_adj_q(cf *Y, const float *G, size_t g_clip_stride, const cf *Gband, c
   Geo g = to_geo(pg);
   const bool band = Gband != nullptr;
   size_t sh = size_t(RPB) * lds_len<Q>() * sizeof(cf);
-  if (!band)
-    return launch("pass_x_adj", KPTR(dev::k_pass_x_adj<Q, 0>), dim3(Q / RPB, nclips), sh, s, [&] {
-      hipLaunchKernelGGL((dev::k_pass_x_adj<Q, 0>), dim3(Q / RPB, nclips), dim3(256), sh, s, Y, G, g_clip_stride,
-                         Gband, g, twQ);
-    });
-  return launch("pass_x_adj", KPTR(dev::k_pass_x_adj<Q, 1>), dim3(Q / RPB, nclips), sh, s, [&] {
-    hipLaunchKernelGGL((dev::k_pass_x_adj<Q, 1>), dim3(Q / RPB, nclips), dim3(256), sh, s, Y, G, g_clip_stride,
-                       Gband, g, twQ);
-  });
+  const bool pr = dev::prunable<Q>(g.b);
+  const dim3 grid(Q / RPB, nclips);
+#define LITHO_PX_ADJ(GIN, PR)                                                                              \
+  return launch("pass_x_adj", KPTR(dev::k_pass_x_adj<Q, GIN, PR>), grid, sh, s, [&] {                      \
+    hipLaunchKernelGGL((dev::k_pass_x_adj<Q, GIN, PR>), grid, dim3(256), sh, s, Y, G, g_clip_stride, Gband, g, \
+                       twQ);                                                                               \
+  })
+  if (!band) {
+    if (pr) LITHO_PX_ADJ(0, true);
+    LITHO_PX_ADJ(0, false);
+  }
+  if (pr) LITHO_PX_ADJ(1, true);
+  LITHO_PX_ADJ(1, false);
+#undef LITHO_PX_ADJ
 }
 
 template <int Q>
@@ -1017,8 +1059,14 @@ int pass_y_adj_q(const cf *V, const cf *bank, double2 *part, const PassGeo &pg, 
   Geo g = to_geo(pg);
   constexpr size_t sh = col_lds<Q>();
   const dim3 grid(col_blocks<Q>(g.nt), g.KC, nclips);
-  return launch("pass_y_adj", KPTR(dev::k_pass_y_adj<Q>), grid, sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_pass_y_adj<Q>, grid, dim3(dev::ColBlock<Q>::threads), sh, s, V, bank, part, g, twQ);
+  if (dev::prunable<Q>(g.b))
+    return launch("pass_y_adj", KPTR(dev::k_pass_y_adj<Q, true>), grid, sh, s, [&] {
+      hipLaunchKernelGGL((dev::k_pass_y_adj<Q, true>), grid, dim3(dev::ColBlock<Q>::threads), sh, s, V, bank, part,
+                         g, twQ);
+    });
+  return launch("pass_y_adj", KPTR(dev::k_pass_y_adj<Q, false>), grid, sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_pass_y_adj<Q, false>), grid, dim3(dev::ColBlock<Q>::threads), sh, s, V, bank, part, g,
+                       twQ);
   });
 }
 
