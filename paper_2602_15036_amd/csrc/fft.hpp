@@ -264,9 +264,48 @@ template <> struct FftPlan<3072> { static constexpr int T = 64; using R = Radice
 // LDS index with one pad slot every 32 complex values, and 4 more slots
 // between the regions of neighbouring transforms: breaks the power-of-two
 // strides of the Stockham scatter across 64 four-byte banks.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+// LDS padding of exchange p (the writes of pass p and the reads of pass
+// p + 1): element x lives at x + M_p (x >> 5).  The multipliers are chosen per
+// plan (bank model: 64 banks of 4 B, 32 lanes per cycle, 8-byte elements) so
+// that both access patterns of every exchange avoid bank conflicts; any M_p
+// keeps the padded addresses affine in the element index, because every write
+// stride is a power of two.
+template <int... Ms>
+struct PadMults {};
 template <int L>
-constexpr int lds_len() { return L + L / 32 + 4; }
+struct PadPlan {
+  using M = PadMults<>;  // all 1
+};
+template <> struct PadPlan<512> { using M = PadMults<1, 4>; };
+template <> struct PadPlan<640> { using M = PadMults<1, 4, 8>; };
+template <> struct PadPlan<768> { using M = PadMults<1, 4>; };
+template <> struct PadPlan<1024> { using M = PadMults<1, 2>; };
+template <> struct PadPlan<1280> { using M = PadMults<1, 4, 8>; };
+template <> struct PadPlan<1536> { using M = PadMults<1, 2, 4>; };
+template <> struct PadPlan<2048> { using M = PadMults<1, 2>; };
+template <> struct PadPlan<2560> { using M = PadMults<1, 4, 0>; };
+template <> struct PadPlan<3072> { using M = PadMults<1, 2>; };
+template <> struct PadPlan<4096> { using M = PadMults<1, 2>; };
+
+template <int P, typename Pack>
+struct PadAt {
+  static constexpr int value = 1;
+};
+template <int P, int M0, int... Ms>
+struct PadAt<P, PadMults<M0, Ms...>> {
+  static constexpr int value = P == 0 ? M0 : PadAt<P - 1, PadMults<Ms...>>::value;
+};
+template <int... Ms>
+constexpr int pad_max(PadMults<Ms...>) {
+  int m = 1;
+  for (int x : {1, Ms...}) m = x > m ? x : m;
+  return m;
+}
+
+template <int M>
+__device__ __forceinline__ int lpad(int i) { return i + M * (i >> 5); }
+template <int L>
+constexpr int lds_len() { return L + pad_max(typename PadPlan<L>::M{}) * (L / 32) + 4; }
 
 // Twiddle table layout.  Pass p (radix R after radices multiplying to S > 1)
 // owns S * (R - 1) consecutive entries starting at tw_offset<p>; entry
@@ -322,8 +361,8 @@ __device__ __forceinline__ int opaque_lane(int x) {
 }
 
 // One Stockham pass of radix R after passes whose radices multiply to S;
-// its twiddles start at entry OFF of the table.
-template <int L, int T, int DIR, int R, int S, int OFF, bool LAST>
+// its twiddles start at entry OFF of the table; its exchange pads by M.
+template <int L, int T, int DIR, int R, int S, int OFF, bool LAST, int M>
 __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ buf, int t,
                                               const cf *__restrict__ tw) {
   constexpr int E = L / T;
@@ -352,28 +391,29 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ b
     } else {
       const int base = (j / S) * S * R + (j % S);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lpad(base + r * S)] = u[r];
+      for (int r = 0; r < R; ++r) buf[lpad<M>(base + r * S)] = u[r];
     }
   }
   if constexpr (!LAST) {
     xsync<T>();
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = buf[lpad(t + T * i)];
+    for (int i = 0; i < E; ++i) v[i] = buf[lpad<M>(t + T * i)];
     xsync<T>();
   }
 }
 
-template <int L, int T, int DIR, int S, int OFF, int R, int... Rest>
+template <int L, int T, int DIR, int S, int OFF, int P, int R, int... Rest>
 __device__ __forceinline__ void run_passes(cf (&v)[L / T], cf *buf, int t, const cf *tw) {
-  stockham_pass<L, T, DIR, R, S, OFF, sizeof...(Rest) == 0>(v, buf, t, tw);
+  stockham_pass<L, T, DIR, R, S, OFF, sizeof...(Rest) == 0, PadAt<P, typename PadPlan<L>::M>::value>(v, buf, t,
+                                                                                                     tw);
   if constexpr (sizeof...(Rest) > 0)
-    run_passes<L, T, DIR, S * R, OFF + (S > 1 ? S * (R - 1) : 0), Rest...>(v, buf, t, tw);
+    run_passes<L, T, DIR, S * R, OFF + (S > 1 ? S * (R - 1) : 0), P + 1, Rest...>(v, buf, t, tw);
 }
 
 template <int L, int DIR, int... Rs>
 __device__ __forceinline__ void fft_impl(cf (&v)[L / FftPlan<L>::T], cf *buf, int t, const cf *tw,
                                          Radices<Rs...>) {
-  run_passes<L, FftPlan<L>::T, DIR, 1, 0, Rs...>(v, buf, t, tw);
+  run_passes<L, FftPlan<L>::T, DIR, 1, 0, 0, Rs...>(v, buf, t, tw);
 }
 
 // Host: fills the table of FftPlan<L> (FP64 angles, rounded once to FP32).
