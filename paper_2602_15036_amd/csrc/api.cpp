@@ -388,8 +388,9 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
     g.KC = (K_use + g.kper - 1) / g.kper;
   }
   const bool resample = g.Q != g.N;
-  // loss partials come from the row pass that applies the resist (N grid)
-  L.nblk = g.N / (256 / pass_threads(g.N));
+  // loss partials come from the row pass that applies the resist (N grid):
+  // one per block; with resampling that pass takes two rows per transform
+  L.nblk = g.N / (256 / pass_threads(g.N)) / (resample ? 2 : 1);
   const size_t N = g.N, Q = g.Q;
   L.b_S1 = align256(size_t(g.nt) * N * kTileCols * sizeof(float2));
   L.b_Mh = align256(size_t(g.nt) * g.B * kTileCols * sizeof(float2));

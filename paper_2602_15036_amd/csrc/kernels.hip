@@ -175,6 +175,9 @@ __device__ __forceinline__ double image_epilogue(const Epi &ep, const Geo &g, in
 //
 // out[clip][jt][y][c] = scale * sum_x in[y][x] exp(-2 pi i kx x / L), |kx| <= h,
 // kx = jt*kC + c - h; the Wp - (2h+1) pad columns are written as zeros.
+// Two real rows share one complex transform: Z = DFT(r0 + i r1) gives
+// DFT(r0)[k] = (Z[k] + conj Z[-k]) / 2 and DFT(r1)[k] = (Z[k] - conj Z[-k]) / 2i,
+// with Z[-k] read back through the transform's LDS region.
 template <int L>
 __global__ __launch_bounds__(256) void k_rows_fwd_real(const float *__restrict__ in, size_t in_clip,
                                                        cf *__restrict__ out, int h, int Wp,
@@ -182,18 +185,34 @@ __global__ __launch_bounds__(256) void k_rows_fwd_real(const float *__restrict__
   constexpr int T = FftPlan<L>::T, E = L / T, RPB = 256 / T;
   extern __shared__ cf smem[];
   const int row = threadIdx.x / T, t = threadIdx.x % T;
-  const int y = blockIdx.x * RPB + row, clip = blockIdx.y;
-  const float *src = in + clip * in_clip + size_t(y) * L;
+  const int y0 = 2 * (blockIdx.x * RPB + row), clip = blockIdx.y;
+  const float *src = in + clip * in_clip + size_t(y0) * L;
+  cf *buf = smem + row * lds_len<L>();
   cf v[E];
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = cmake(src[t + T * i], 0.0f);
-  fft<L, -1>(v, smem + row * lds_len<L>(), t, tw);
-  store_band_row<L, T>(v, out + size_t(clip) * (Wp / kC) * L * kC, y, t, h, Wp, scale);
+  for (int i = 0; i < E; ++i) v[i] = cmake(src[t + T * i], src[L + t + T * i]);
+  fft<L, -1>(v, buf, t, tw);
+#pragma unroll
+  for (int i = 0; i < E; ++i) buf[t + T * i] = v[i];
+  xsync<T>();
+  cf w[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const cf a = v[i], b = buf[(L - t - T * i) & (L - 1)];
+    v[i] = cmake(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+    w[i] = cmake(0.5f * (a.y + b.y), 0.5f * (b.x - a.x));
+  }
+  cf *dst = out + size_t(clip) * (Wp / kC) * L * kC;
+  store_band_row<L, T>(v, dst, y0, t, h, Wp, scale);
+  store_band_row<L, T>(w, dst, y0 + 1, t, h, Wp, scale);
 }
 
 // ------------------------------------------------------------ band rows -> real rows
 // v = sum_kx in(y, kx) exp(+2 pi i kx x / L); MODE 0: out[y][x] = scale Re v;
-// MODE 1: I = scale Re v through the image / resist epilogue (L == N).
+// MODE 1: I = scale Re v through the image / resist epilogue (L == N).  The
+// image rows are real, so their band rows are Hermitian and MODE 1 sends two
+// rows through one complex transform: X_y0 + i X_y1 yields row y0 in the real
+// part and row y1 in the imaginary part (rows 2 (block RPB + row) and + 1).
 template <int L, int MODE>
 __global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in, int h, int Wp,
                                                        float *__restrict__ out, Epi ep, Geo g,
@@ -201,18 +220,30 @@ __global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in
   constexpr int T = FftPlan<L>::T, E = L / T, RPB = 256 / T;
   extern __shared__ cf smem[];
   const int row = threadIdx.x / T, t = threadIdx.x % T;
-  const int y = blockIdx.x * RPB + row, clip = blockIdx.y;
+  const int clip = blockIdx.y;
+  const cf *src = in + size_t(clip) * (Wp / kC) * L * kC;
   cf v[E];
-  load_band_row<L, T>(v, in + size_t(clip) * (Wp / kC) * L * kC, y, t, h);
-  fft<L, +1>(v, smem + row * lds_len<L>(), t, tw);
   if constexpr (MODE == 0) {
+    const int y = blockIdx.x * RPB + row;
+    load_band_row<L, T>(v, src, y, t, h);
+    fft<L, +1>(v, smem + row * lds_len<L>(), t, tw);
     float *dst = out + (size_t(clip) * L + y) * L;
 #pragma unroll
     for (int i = 0; i < E; ++i) dst[t + T * i] = scale * v[i].x;
   } else {
+    const int y0 = 2 * (blockIdx.x * RPB + row);
+    cf b[E];
+    load_band_row<L, T>(v, src, y0, t, h);
+    load_band_row<L, T>(b, src, y0 + 1, t, h);
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = cmake(v[i].x - b[i].y, v[i].y + b[i].x);
+    fft<L, +1>(v, smem + row * lds_len<L>(), t, tw);
     double lsum = 0.0;
 #pragma unroll
-    for (int i = 0; i < E; ++i) lsum += image_epilogue(ep, g, clip, y, t + T * i, scale * v[i].x);
+    for (int i = 0; i < E; ++i) {
+      lsum += image_epilogue(ep, g, clip, y0, t + T * i, scale * v[i].x);
+      lsum += image_epilogue(ep, g, clip, y0 + 1, t + T * i, scale * v[i].y);
+    }
     if (ep.target) {
       const double s = block_sum(lsum, reinterpret_cast<double *>(smem));
       if (threadIdx.x == 0) ep.loss_part[(size_t(clip) * g.P + g.p) * gridDim.x + blockIdx.x] = s;
@@ -948,9 +979,9 @@ int rows_fwd_real_l(const char *name, const float *in, size_t in_clip, cf *out, 
                     float scale, int nclips, hipStream_t s) {
   constexpr int T = FftPlan<L>::T, RPB = 256 / T;
   size_t sh = size_t(RPB) * lds_len<L>() * sizeof(cf);
-  return launch(name, KPTR(dev::k_rows_fwd_real<L>), dim3(L / RPB, nclips), sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_rows_fwd_real<L>, dim3(L / RPB, nclips), dim3(256), sh, s, in, in_clip, out, h, Wp,
-                       tw, scale);
+  const dim3 grid(L / RPB / 2, nclips);  // two rows per transform
+  return launch(name, KPTR(dev::k_rows_fwd_real<L>), grid, sh, s, [&] {
+    hipLaunchKernelGGL(dev::k_rows_fwd_real<L>, grid, dim3(256), sh, s, in, in_clip, out, h, Wp, tw, scale);
   });
 }
 
@@ -962,9 +993,9 @@ int rows_inv_real_l(const char *name, const cf *in, int h, int Wp, float *out, c
   sh = std::max(sh, size_t(256) * sizeof(double));
   Geo g = to_geo(pg);
   Epi e = to_epi(ep);
-  return launch(name, KPTR(dev::k_rows_inv_real<L, MODE>), dim3(L / RPB, nclips), sh, s, [&] {
-    hipLaunchKernelGGL((dev::k_rows_inv_real<L, MODE>), dim3(L / RPB, nclips), dim3(256), sh, s, in, h, Wp, out,
-                       e, g, tw, scale);
+  const dim3 grid(L / RPB / (MODE == 1 ? 2 : 1), nclips);  // MODE 1: two rows per transform
+  return launch(name, KPTR(dev::k_rows_inv_real<L, MODE>), grid, sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_rows_inv_real<L, MODE>), grid, dim3(256), sh, s, in, h, Wp, out, e, g, tw, scale);
   });
 }
 
