@@ -18,10 +18,17 @@ import math
 import numpy as np
 
 
+def _sigma_max(spec):
+    """Largest source radius: sigma_out for lattice sources, max |sigma| for points."""
+    if spec.source == "points":
+        return max(math.hypot(sx, sy) for sx, sy, _ in spec.points)
+    return spec.sigma_out
+
+
 def band_geometry(spec):
     """Return (b, B, R): band half-width, band side 2b+1, pupil radius (index units)."""
     R = spec.na * spec.n * spec.pixel_nm / spec.wavelength_nm
-    b = int(math.floor((1.0 + spec.sigma_out) * R))
+    b = int(math.floor((1.0 + _sigma_max(spec)) * R))
     return b, 2 * b + 1, R
 
 
@@ -35,8 +42,14 @@ def source_points(spec):
     All kept points weigh the same and the weights sum to one (the paper calls
     S the normalised source intensity).
 
+    The y-dipole keeps |i| <= |j| instead.  A "points" source lists its own
+    (sigma_x, sigma_y, weight) samples; the weights are normalised to sum one.
+
     Returns (sx, sy, w) as float64 arrays.
     """
+    if spec.source == "points":
+        pts = np.asarray(spec.points, dtype=np.float64).reshape(-1, 3)
+        return pts[:, 0].copy(), pts[:, 1].copy(), pts[:, 2] / pts[:, 2].sum()
     G = spec.source_grid
     h = (G - 1) // 2
     lo = spec.sigma_in ** 2 * h * h
@@ -48,6 +61,8 @@ def source_points(spec):
             ok = (lo - 1e-9) <= r2 <= (hi + 1e-9)
             if spec.source == "dipole_x":
                 ok = ok and abs(j) <= abs(i)
+            elif spec.source == "dipole_y":
+                ok = ok and abs(i) <= abs(j)
             elif spec.source != "annular":
                 raise ValueError(f"unknown source kind {spec.source!r}")
             if ok:

@@ -152,20 +152,21 @@ def loss_and_residual(I, T, slope, threshold):
     return float(np.sum(d * d)), 2.0 * d * slope * Z * (1.0 - Z)
 
 
-def loss_value(m, T, banks, slope, threshold, method="direct"):
-    """Through-focus loss: sum over planes p of sum_r (Z_p - T)^2.
+def loss_value(m, T, banks, slope, threshold, method="direct", weights=None):
+    """Through-focus loss: sum over planes p of w_p sum_r (Z_p - T)^2.
 
-    ``banks`` is a list of (lam, phi), one per focus plane.
+    ``banks`` is a list of (lam, phi), one per focus plane; ``weights`` the
+    plane weights w_p (default 1 each).
     """
     total = 0.0
-    for lam, phi in banks:
+    for p, (lam, phi) in enumerate(banks):
         I = image(m, lam, phi, method)
         L, _ = loss_and_residual(I, T, slope, threshold)
-        total += L
+        total += (1.0 if weights is None else weights[p]) * L
     return total
 
 
-def gradient(m, T, banks, slope, threshold, method="direct", G_override=None):
+def gradient(m, T, banks, slope, threshold, method="direct", G_override=None, weights=None):
     """ILT adjoint: dL/dm for the SOCS image (pixel-based ILT gradient).
 
     The paper names the mask gradient (Sec. III-B, Eq. 9's dI/dM channel) but
@@ -176,7 +177,8 @@ def gradient(m, T, banks, slope, threshold, method="direct", G_override=None):
 
     with G_p = dL/dI_p.  If ``G_override`` (a list of [n, n] arrays, one per
     plane) is given, it replaces the sigmoid-loss residual (vector-Jacobian
-    product mode).  Returns (loss, grad, images).
+    product mode).  ``weights`` (plane weights w_p, default 1) scale each
+    plane's loss and residual.  Returns (loss, grad, images).
     """
     n = m.shape[0]
     grad = np.zeros((n, n))
@@ -191,7 +193,9 @@ def gradient(m, T, banks, slope, threshold, method="direct", G_override=None):
         images.append(I)
         if G_override is None:
             L, G = loss_and_residual(I, T, slope, threshold)
-            total += L
+            wp = 1.0 if weights is None else weights[p]
+            total += wp * L
+            G = wp * G
         else:
             G = G_override[p]
         for kk in range(lam.size):
@@ -206,7 +210,7 @@ def gradient(m, T, banks, slope, threshold, method="direct", G_override=None):
     return total, grad, images
 
 
-def fd_gradient(m, T, banks, slope, threshold, pixels, h=1e-5, method="direct"):
+def fd_gradient(m, T, banks, slope, threshold, pixels, h=1e-5, method="direct", weights=None):
     """Central finite differences of ``loss_value`` at the listed pixels (FP64)."""
     out = []
     for (y, x) in pixels:
@@ -214,8 +218,8 @@ def fd_gradient(m, T, banks, slope, threshold, pixels, h=1e-5, method="direct"):
         mp[y, x] += h
         mm = m.copy()
         mm[y, x] -= h
-        out.append((loss_value(mp, T, banks, slope, threshold, method)
-                    - loss_value(mm, T, banks, slope, threshold, method)) / (2 * h))
+        out.append((loss_value(mp, T, banks, slope, threshold, method, weights)
+                    - loss_value(mm, T, banks, slope, threshold, method, weights)) / (2 * h))
     return np.array(out)
 
 

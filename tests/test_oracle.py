@@ -325,3 +325,52 @@ def test_gradient_matches_central_finite_differences(method):
     got = np.array([g[p] for p in pix])
     assert np.abs(got - fd).max() < 1e-7 * np.abs(fd).max()
     assert abs(L - O.loss_value(m, T, banks, 50.0, 0.3, method)) < 1e-12 * L
+
+
+# ---------------------------------------------------------------- source kinds, plane weights
+
+def test_y_dipole_is_the_transposed_x_dipole():
+    # the y-dipole keeps |i| <= |j|: the x-dipole mirrored about the diagonal,
+    # so imaging the transposed mask gives the transposed image
+    sx, sy, _ = O.source_points(DIP64)
+    tx, ty, _ = O.source_points(DIP64.with_(source="dipole_y"))
+    assert sorted(zip(sy.tolist(), sx.tolist())) == sorted(zip(tx.tolist(), ty.tolist()))
+    lx, px = O.socs_kernels(DIP64, 0.0, K=60)
+    ly, py = O.socs_kernels(DIP64.with_(source="dipole_y"), 0.0, K=60)
+    assert np.allclose(lx, ly, rtol=0, atol=1e-13 * lx[0])
+    m = W.manhattan_mask(64, 4, n_rects=6, side_min=3, side_max=20)
+    Ix = O.image(m, lx, px)
+    Iy = O.image(np.ascontiguousarray(m.T), ly, py)
+    assert np.abs(Iy - Ix.T).max() < 1e-12 * Ix.max()
+    # and the x-dipole image is not itself transpose-symmetric (the test has teeth)
+    assert np.abs(O.image(np.ascontiguousarray(m.T), lx, px) - Ix.T).max() > 1e-3 * Ix.max()
+
+
+def test_point_list_source_reproduces_the_lattice_source():
+    # the annular lattice written out as explicit points (unnormalised weights)
+    sx, sy, w = O.source_points(ANN64)
+    pts = tuple((float(a), float(b), 3.0) for a, b in zip(sx, sy))
+    spec = ANN64.with_(source="points", points=pts)
+    assert O.band_geometry(spec) == O.band_geometry(ANN64)
+    px, py, pw = O.source_points(spec)
+    assert np.array_equal(px, sx) and np.array_equal(py, sy) and np.allclose(pw, w, rtol=0, atol=1e-16)
+    la, pa = O.socs_kernels(ANN64, 0.0, K=8)
+    lp, pp = O.socs_kernels(spec, 0.0, K=8)
+    m = W.curvilinear_mask(64, 9)
+    assert np.abs(O.image(m, lp, pp) - O.image(m, la, pa)).max() < 1e-13
+
+
+def test_plane_weighted_gradient_matches_central_finite_differences():
+    spec = W.fd_clip_optics(32)
+    banks = [O.socs_kernels(spec, F, K=10) for F in spec.focus_nm]
+    m = W.curvilinear_mask(32, 3)
+    T = W.manhattan_mask(32, 4, n_rects=3, side_min=4, side_max=10)
+    wts = [0.25, 1.0, 2.5]
+    L, g, _ = O.gradient(m, T, banks, 50.0, 0.3, weights=wts)
+    parts = [O.gradient(m, T, [bk], 50.0, 0.3) for bk in banks]
+    assert abs(L - sum(w * p[0] for w, p in zip(wts, parts))) < 1e-12 * L
+    rng = np.random.default_rng(8)
+    pix = [tuple(int(v) for v in rng.integers(0, 32, 2)) for _ in range(10)]
+    fd = O.fd_gradient(m, T, banks, 50.0, 0.3, pix, h=1e-5, weights=wts)
+    got = np.array([g[p] for p in pix])
+    assert np.abs(got - fd).max() < 1e-7 * np.abs(fd).max()

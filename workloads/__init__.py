@@ -34,9 +34,11 @@ __all__ = [
 class OpticsSpec:
     """Optical settings of one workload (plain numbers, no arithmetic).
 
-    ``source`` is ``"annular"`` or ``"dipole_x"``; ``sigma_in``/``sigma_out`` are
-    in units of NA; the source is sampled on a ``source_grid`` x ``source_grid``
-    lattice over [-1, 1]^2.  ``focus_nm`` lists the focus planes (one bank each).
+    ``source`` is ``"annular"``, ``"dipole_x"``, ``"dipole_y"`` or ``"points"``;
+    ``sigma_in``/``sigma_out`` are in units of NA; lattice sources are sampled on
+    a ``source_grid`` x ``source_grid`` lattice over [-1, 1]^2.  ``"points"``
+    takes ``points``: a tuple of (sigma_x, sigma_y, weight) triples.
+    ``focus_nm`` lists the focus planes (one bank each).
     """
 
     n: int
@@ -49,6 +51,7 @@ class OpticsSpec:
     source_grid: int = 15
     focus_nm: tuple = (0.0,)
     K: int = 8
+    points: tuple = ()
 
     def with_(self, **kw) -> "OpticsSpec":
         return replace(self, **kw)
