@@ -53,12 +53,15 @@ enum {
   LITHO_E_NOTFOUND = -6      /* serve: unknown or already collected ticket */
 };
 
-/* Source shapes (Eq. 2's S), sampled on a G x G lattice over [-1, 1]^2 in units
- * of NA with integer coordinates (i, j), sigma = (i, j) / ((G - 1) / 2).  A
- * point is kept when sigma_in^2 h^2 <= i^2 + j^2 <= sigma_out^2 h^2 with
- * h = (G - 1) / 2; the x-dipole also requires |j| <= |i|.  Kept points weigh
- * the same and the weights sum to one. */
-enum { LITHO_SRC_ANNULAR = 0, LITHO_SRC_DIPOLE_X = 1 };
+/* Source shapes (Eq. 2's S).  Lattice sources are sampled on a G x G lattice
+ * over [-1, 1]^2 in units of NA with integer coordinates (i, j),
+ * sigma = (i, j) / ((G - 1) / 2).  A point is kept when
+ * sigma_in^2 h^2 <= i^2 + j^2 <= sigma_out^2 h^2 with h = (G - 1) / 2; the
+ * x-dipole also requires |j| <= |i|, the y-dipole |i| <= |j|.  Kept points
+ * weigh the same and the weights sum to one.  LITHO_SRC_POINTS takes the
+ * caller's samples (optics.src_points); their weights are normalised to sum
+ * one. */
+enum { LITHO_SRC_ANNULAR = 0, LITHO_SRC_DIPOLE_X = 1, LITHO_SRC_DIPOLE_Y = 2, LITHO_SRC_POINTS = 3 };
 
 /* Arithmetic of the band DFT stages (the column transforms between the
  * cropped pupil band and the inner grid; north of those every pass stays FP32,
@@ -90,6 +93,12 @@ typedef struct litho_optics {
   const double *focus_nm;   /* h_[n_focus] focus offsets F (copied) */
   int K;                    /* SOCS kernels kept per plane (Eq. 3), 1..n_source */
   double dose;              /* D of Eq. 1 (scales I); 0 is taken as 1 */
+  /* LITHO_SRC_POINTS only (else ignored): h_[n_src_points][3] samples
+   * (sigma_x, sigma_y, weight >= 0), sigma in units of NA with |sigma| <= 1,
+   * copied.  sigma_in, sigma_out and source_grid are then ignored; the band is
+   * set by the largest |sigma|. */
+  const double *src_points;
+  int n_src_points;
 } litho_optics_t;
 
 typedef struct litho_bank litho_bank_t;
@@ -97,7 +106,7 @@ typedef struct litho_bank litho_bank_t;
 /* Geometry and spectrum of a bank. */
 typedef struct litho_bank_info {
   int n;                    /* grid side */
-  int b;                    /* band half-width: |kx|, |ky| <= b, b = floor((1 + sigma_out) R) */
+  int b;                    /* band half-width: |kx|, |ky| <= b, b = floor((1 + sigma_max) R) */
   int B;                    /* band side 2b + 1 */
   int K;                    /* kernels per plane */
   int n_focus;              /* planes */
@@ -105,6 +114,10 @@ typedef struct litho_bank_info {
   int inner_grid;           /* side of the grid the per-kernel transforms run on */
   double pupil_radius;      /* R = NA n p / lambda in frequency-index units */
   size_t device_bytes;      /* device memory held by the bank (without workspaces) */
+  double clear_field;       /* D sum_k lambda_k |Phi_k(0)|^2 of the first plane: the image of a clear mask */
+  double degeneracy_gap;    /* min over planes of (lambda_K - lambda_{K+1}) / lambda_1; 1 when K is the
+                             * source rank, 0 for a loaded bank (unknown).  A cut inside a degenerate
+                             * pair (gap ~ 0) makes the truncated image depend on the eigenbasis. */
 } litho_bank_info_t;
 
 /* Build the SOCS kernel bank of Eqs. 2-3 on the host in FP64 and upload it.
@@ -168,13 +181,14 @@ int litho_image(const litho_bank_t *bank, const float *d_mask, int batch, int K_
 typedef struct litho_resist {
   double slope;       /* a of the sigmoid resist (e.g. 50) */
   double threshold;   /* t, relative to the open-frame intensity (e.g. 0.3) */
+  const double *plane_weight;  /* h_[n_focus] weights w_p of the planes' losses, or NULL (all 1) */
 } litho_resist_t;
 
 /* Forward image plus the ILT adjoint (mask gradient).
  * Two modes:
  *   fused loss  (d_target != NULL): Z = sigmoid(a (I - t)),
- *                L = sum_planes sum_r (Z - T)^2 per clip,
- *                G = dL/dI = 2 (Z - T) a Z (1 - Z); resist must be non-NULL.
+ *                L = sum_planes w_p sum_r (Z - T)^2 per clip,
+ *                G = dL/dI = 2 w_p (Z - T) a Z (1 - Z); resist must be non-NULL.
  *   VJP         (d_target == NULL): G = d_grad_image, [batch][n_focus][n][n].
  * For each plane and kernel the coherent field E_k is recomputed (never
  * stored) and correlated with G through the conjugate kernel:

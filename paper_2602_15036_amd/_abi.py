@@ -18,6 +18,8 @@ LITHO_E_NOTFOUND = -6
 
 LITHO_SRC_ANNULAR = 0
 LITHO_SRC_DIPOLE_X = 1
+LITHO_SRC_DIPOLE_Y = 2
+LITHO_SRC_POINTS = 3
 LITHO_PREC_FP32 = 0
 LITHO_PREC_F16X3 = 1
 LITHO_PREC_BF16X3 = 2
@@ -38,7 +40,7 @@ class Optics(C.Structure):
         ("n", C.c_int), ("pixel_nm", C.c_double), ("wavelength_nm", C.c_double), ("na", C.c_double),
         ("source_kind", C.c_int), ("source_grid", C.c_int), ("sigma_in", C.c_double),
         ("sigma_out", C.c_double), ("n_focus", C.c_int), ("focus_nm", C.POINTER(C.c_double)),
-        ("K", C.c_int), ("dose", C.c_double),
+        ("K", C.c_int), ("dose", C.c_double), ("src_points", C.POINTER(C.c_double)), ("n_src_points", C.c_int),
     ]
 
 
@@ -46,12 +48,12 @@ class BankInfo(C.Structure):
     _fields_ = [
         ("n", C.c_int), ("b", C.c_int), ("B", C.c_int), ("K", C.c_int), ("n_focus", C.c_int),
         ("n_source", C.c_int), ("inner_grid", C.c_int), ("pupil_radius", C.c_double),
-        ("device_bytes", C.c_size_t),
+        ("device_bytes", C.c_size_t), ("clear_field", C.c_double), ("degeneracy_gap", C.c_double),
     ]
 
 
 class Resist(C.Structure):
-    _fields_ = [("slope", C.c_double), ("threshold", C.c_double)]
+    _fields_ = [("slope", C.c_double), ("threshold", C.c_double), ("plane_weight", C.POINTER(C.c_double))]
 
 
 class ServeCfg(C.Structure):

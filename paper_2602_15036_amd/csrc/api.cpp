@@ -304,6 +304,12 @@ extern "C" int litho_kernels_info(const litho_bank_t *bk, litho_bank_info_t *inf
   info->inner_grid = bk->Q;
   info->pupil_radius = bk->host.R;
   info->device_bytes = bk->phi_bytes + size_t(bk->host.n) * sizeof(float2);
+  const HostBank &h = bk->host;
+  double cf = 0.0;
+  for (int k = 0; k < h.K; ++k)
+    cf += h.lambda[size_t(k)] * std::norm(h.phi[(size_t(k) * h.B + h.b) * h.B + h.b]);
+  info->clear_field = h.dose * cf;
+  info->degeneracy_gap = h.gap.empty() ? 0.0 : *std::min_element(h.gap.begin(), h.gap.end());
   return LITHO_OK;
 }
 
@@ -431,7 +437,8 @@ int acquire_workspace(litho_bank *bk, hipStream_t s, size_t bytes, char **out) {
 // Forward (and optionally adjoint) over one chunk of clips.
 int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, int n, const float *target,
               const float *grad_image, float *image, double *loss, float *grad_mask, bool grad, hipStream_t s,
-              double slope, double thr, int prec, const void *gemm_fwd, const void *gemm_adj) {
+              double slope, double thr, const double *plane_w, int prec, const void *gemm_fwd,
+              const void *gemm_adj) {
   PassGeo g = L.g;
   g.slope = slope;
   g.thr = thr;
@@ -460,6 +467,7 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
   ep.loss_part = lossp;
   for (int pl = 0; pl < g.P; ++pl) {
     g.p = pl;
+    g.pw = plane_w ? plane_w[pl] : 1.0;
     if (prec == LITHO_PREC_FP32)
       LITHO_TRY(run_pass_y_fwd(bk->d_phi, Mh, Y, g, twQ, n, s));
     else
@@ -548,8 +556,8 @@ int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, c
                         d_grad_image ? d_grad_image + size_t(c0) * P * NN : nullptr,
                         d_image ? d_image + size_t(c0) * P * NN : nullptr, d_loss ? d_loss + c0 : nullptr,
                         d_grad_mask ? d_grad_mask + size_t(c0) * NN : nullptr, grad, s,
-                        resist ? resist->slope : 0.0, resist ? resist->threshold : 0.0, prec, gemm_fwd,
-                        gemm_adj));
+                        resist ? resist->slope : 0.0, resist ? resist->threshold : 0.0,
+                        resist ? resist->plane_weight : nullptr, prec, gemm_fwd, gemm_adj));
   }
   return LITHO_OK;
 }

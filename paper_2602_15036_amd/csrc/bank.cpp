@@ -19,6 +19,13 @@ namespace litho {
 
 std::vector<SourcePoint> sample_source(const litho_optics_t &o) {
   std::vector<SourcePoint> pts;
+  if (o.source_kind == LITHO_SRC_POINTS) {
+    double sum = 0.0;
+    for (int s = 0; s < o.n_src_points; ++s) sum += o.src_points[3 * s + 2];
+    for (int s = 0; s < o.n_src_points; ++s)
+      pts.push_back({o.src_points[3 * s], o.src_points[3 * s + 1], o.src_points[3 * s + 2] / sum});
+    return pts;
+  }
   const int h = (o.source_grid - 1) / 2;
   const double lo = o.sigma_in * o.sigma_in * h * h;
   const double hi = o.sigma_out * o.sigma_out * h * h;
@@ -27,6 +34,7 @@ std::vector<SourcePoint> sample_source(const litho_optics_t &o) {
       const double r2 = double(i * i + j * j);
       bool keep = (lo - 1e-9) <= r2 && r2 <= (hi + 1e-9);
       if (o.source_kind == LITHO_SRC_DIPOLE_X) keep = keep && std::abs(j) <= std::abs(i);
+      if (o.source_kind == LITHO_SRC_DIPOLE_Y) keep = keep && std::abs(i) <= std::abs(j);
       if (keep) pts.push_back({double(i) / h, double(j) / h, 0.0});
     }
   }
@@ -100,15 +108,40 @@ void hermitian_jacobi(int n, std::vector<cd> &a, std::vector<double> &w, std::ve
 }
 
 int build_host_bank(const litho_optics_t &o, HostBank &hb) {
-  if (o.n <= 0 || !(o.pixel_nm > 0) || !(o.wavelength_nm > 0) || !(o.na > 0) || o.source_grid < 3 ||
-      (o.source_grid % 2) == 0 || o.sigma_in < 0 || o.sigma_out < o.sigma_in || o.sigma_out > 1.0 ||
-      o.n_focus < 1 || o.n_focus > 8 || !o.focus_nm || o.K < 1) {
+  const bool points = o.source_kind == LITHO_SRC_POINTS;
+  if (o.n <= 0 || !(o.pixel_nm > 0) || !(o.wavelength_nm > 0) || !(o.na > 0) || o.n_focus < 1 ||
+      o.n_focus > 8 || !o.focus_nm || o.K < 1 ||
+      (!points && (o.source_grid < 3 || (o.source_grid % 2) == 0 || o.sigma_in < 0 || o.sigma_out < o.sigma_in ||
+                   o.sigma_out > 1.0))) {
     set_error("litho_kernels_build: invalid optics");
     return LITHO_E_INVALID;
   }
-  if (o.source_kind != LITHO_SRC_ANNULAR && o.source_kind != LITHO_SRC_DIPOLE_X) {
+  if (o.source_kind < LITHO_SRC_ANNULAR || o.source_kind > LITHO_SRC_POINTS) {
     set_error("litho_kernels_build: unknown source kind %d", o.source_kind);
     return LITHO_E_INVALID;
+  }
+  double sigma_max = o.sigma_out;
+  if (points) {
+    if (!o.src_points || o.n_src_points < 1) {
+      set_error("litho_kernels_build: a point source needs src_points");
+      return LITHO_E_INVALID;
+    }
+    double wsum = 0.0;
+    sigma_max = 0.0;
+    for (int s = 0; s < o.n_src_points; ++s) {
+      const double sx = o.src_points[3 * s], sy = o.src_points[3 * s + 1], w = o.src_points[3 * s + 2];
+      const double r = std::hypot(sx, sy);
+      if (!(w >= 0.0) || !(r <= 1.0)) {
+        set_error("litho_kernels_build: source point %d has |sigma| > 1 or a negative weight", s);
+        return LITHO_E_INVALID;
+      }
+      sigma_max = std::max(sigma_max, r);
+      wsum += w;
+    }
+    if (!(wsum > 0.0)) {
+      set_error("litho_kernels_build: the source weights sum to zero");
+      return LITHO_E_INVALID;
+    }
   }
   const std::vector<SourcePoint> src = sample_source(o);
   const int ns = int(src.size());
@@ -121,7 +154,7 @@ int build_host_bank(const litho_optics_t &o, HostBank &hb) {
     return LITHO_E_INVALID;
   }
   const double R = o.na * o.n * o.pixel_nm / o.wavelength_nm;
-  const int b = int(std::floor((1.0 + o.sigma_out) * R));
+  const int b = int(std::floor((1.0 + sigma_max) * R));
   const int B = 2 * b + 1;
   if (B > o.n) {
     set_error("litho_kernels_build: band side %d exceeds the grid side %d (undersampled clip)", B, o.n);

@@ -67,6 +67,7 @@ struct Geo {
   int kper;   // kernels per k-chunk
   float dose;
   float slope, thr;
+  float pw;   // weight of the current plane's loss
 };
 
 // Outputs of the image epilogue (image, resist, loss, residual).
@@ -157,15 +158,16 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 }
 
 // Image epilogue at pixel (y, x) of the N grid: image write, sigmoid resist,
-// residual G = 2 (Z - T) a Z (1 - Z); returns (Z - T)^2 (0 without target).
+// residual G = 2 w (Z - T) a Z (1 - Z); returns w (Z - T)^2 (0 without
+// target), w the plane's loss weight.
 __device__ __forceinline__ double image_epilogue(const Epi &ep, const Geo &g, int clip, int y, int x, float I) {
   const size_t NN = size_t(g.N) * g.N;
   if (ep.image) ep.image[(size_t(clip) * g.P + g.p) * NN + size_t(y) * g.N + x] = I;
   if (!ep.target) return 0.0;
   const float z = 1.0f / (1.0f + expf(-g.slope * (I - g.thr)));
   const float d = z - ep.target[size_t(clip) * NN + size_t(y) * g.N + x];
-  ep.G[size_t(clip) * NN + size_t(y) * g.N + x] = 2.0f * d * g.slope * z * (1.0f - z);
-  return double(d) * double(d);
+  ep.G[size_t(clip) * NN + size_t(y) * g.N + x] = 2.0f * g.pw * d * g.slope * z * (1.0f - z);
+  return double(g.pw) * double(d) * double(d);
 }
 
 // ------------------------------------------------------------ real rows -> band
@@ -934,7 +936,7 @@ Geo to_geo(const PassGeo &pg) {
   g.N = pg.N; g.Q = pg.Q; g.b = pg.b; g.B = pg.B; g.Bp = pg.Bp; g.nt = pg.nt;
   g.D = pg.D; g.Dp = pg.Dp; g.ntD = pg.ntD;
   g.K = pg.K; g.Kbank = pg.Kbank; g.P = pg.P; g.p = pg.p; g.KC = pg.KC; g.kper = pg.kper;
-  g.dose = float(pg.dose); g.slope = float(pg.slope); g.thr = float(pg.thr);
+  g.dose = float(pg.dose); g.slope = float(pg.slope); g.thr = float(pg.thr); g.pw = float(pg.pw);
   return g;
 }
 

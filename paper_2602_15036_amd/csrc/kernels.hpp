@@ -24,6 +24,7 @@ struct PassGeo {
   int P = 1, p = 0;
   int KC = 1, kper = 1;  // k-chunks of the adjoint column pass
   double dose = 1.0, slope = 0.0, thr = 0.0;
+  double pw = 1.0;       // weight of the current plane's loss
 };
 
 // Outputs of the image epilogue.

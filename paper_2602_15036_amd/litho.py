@@ -53,7 +53,8 @@ def _addr(t: Optional[torch.Tensor], what: str, dtype=torch.float32):
     return None if p is None else p.value
 
 
-SOURCE_KINDS = {"annular": A.LITHO_SRC_ANNULAR, "dipole_x": A.LITHO_SRC_DIPOLE_X}
+SOURCE_KINDS = {"annular": A.LITHO_SRC_ANNULAR, "dipole_x": A.LITHO_SRC_DIPOLE_X,
+                "dipole_y": A.LITHO_SRC_DIPOLE_Y, "points": A.LITHO_SRC_POINTS}
 
 
 class Bank:
@@ -67,17 +68,25 @@ class Bank:
         self.n_focus, self.n_source = info.n_focus, info.n_source
         self.inner_grid, self.pupil_radius = info.inner_grid, info.pupil_radius
         self.device_bytes = info.device_bytes
+        self.clear_field, self.degeneracy_gap = info.clear_field, info.degeneracy_gap
 
     @classmethod
     def build(cls, n: int, pixel_nm: float, na: float, source: str = "annular",
               sigma_in: float = 0.5, sigma_out: float = 0.8, wavelength_nm: float = 13.5,
               source_grid: int = 15, focus_nm: Sequence[float] = (0.0,), K: int = 8,
-              dose: float = 1.0) -> "Bank":
+              dose: float = 1.0, points: Sequence[Sequence[float]] = ()) -> "Bank":
+        """points: (sigma_x, sigma_y, weight) samples for source="points"."""
         focus = (C.c_double * len(focus_nm))(*[float(f) for f in focus_nm])
+        flat = [float(v) for p in points for v in p]
+        if len(flat) != 3 * len(points):
+            raise ValueError("points must be (sigma_x, sigma_y, weight) triples")
+        pts = (C.c_double * max(1, len(flat)))(*flat)
         o = A.Optics(n=n, pixel_nm=pixel_nm, wavelength_nm=wavelength_nm, na=na,
                      source_kind=SOURCE_KINDS[source], source_grid=source_grid,
                      sigma_in=sigma_in, sigma_out=sigma_out, n_focus=len(focus_nm),
-                     focus_nm=C.cast(focus, C.POINTER(C.c_double)), K=K, dose=dose)
+                     focus_nm=C.cast(focus, C.POINTER(C.c_double)), K=K, dose=dose,
+                     src_points=C.cast(pts, C.POINTER(C.c_double)) if points else None,
+                     n_src_points=len(points))
         h = C.c_void_p()
         _check(_lib.litho_kernels_build(C.byref(o), C.byref(h)), "litho_kernels_build")
         return cls(h)
@@ -88,7 +97,8 @@ class Bank:
         return cls.build(n=spec.n, pixel_nm=spec.pixel_nm, na=spec.na, source=spec.source,
                          sigma_in=spec.sigma_in, sigma_out=spec.sigma_out,
                          wavelength_nm=spec.wavelength_nm, source_grid=spec.source_grid,
-                         focus_nm=tuple(spec.focus_nm), K=spec.K if K is None else K)
+                         focus_nm=tuple(spec.focus_nm), K=spec.K if K is None else K,
+                         points=tuple(getattr(spec, "points", ()) or ()))
 
     @classmethod
     def load(cls, n: int, lam: np.ndarray, phi: np.ndarray) -> "Bank":
@@ -175,9 +185,11 @@ def image(bank: Bank, mask: torch.Tensor, K_use: Optional[int] = None,
 
 def image_grad(bank: Bank, mask: torch.Tensor, target: Optional[torch.Tensor] = None,
                slope: float = 50.0, threshold: float = 0.3, grad_image: Optional[torch.Tensor] = None,
-               K_use: Optional[int] = None, want_image: bool = True, stream=None, prec="fp32"):
+               K_use: Optional[int] = None, want_image: bool = True, stream=None, prec="fp32",
+               plane_weights: Optional[Sequence[float]] = None):
     """Image, loss and mask gradient (fused sigmoid-L2 loss) or a VJP with dL/dI.
 
+    plane_weights: loss weight of each focus plane (fused mode; default 1 each).
     Returns (image or None, loss [batch] float64 or None, grad [batch, n, n]).
     """
     mask = _mask_batch(mask, bank.n)
@@ -192,7 +204,13 @@ def image_grad(bank: Bank, mask: torch.Tensor, target: Optional[torch.Tensor] = 
     if target is not None:
         target = _mask_batch(target, bank.n)
         loss = torch.empty((batch,), device=dev, dtype=torch.float64)
-        resist = A.Resist(slope=slope, threshold=threshold)
+        pw = None
+        if plane_weights is not None:
+            if len(plane_weights) != bank.n_focus:
+                raise ValueError(f"plane_weights needs {bank.n_focus} values")
+            pw = (C.c_double * bank.n_focus)(*[float(v) for v in plane_weights])
+        resist = A.Resist(slope=slope, threshold=threshold,
+                          plane_weight=None if pw is None else C.cast(pw, C.POINTER(C.c_double)))
     if grad_image is not None and grad_image.shape != (batch, bank.n_focus, bank.n, bank.n):
         raise ValueError("grad_image must be [batch, n_focus, n, n]")
     _check(_lib.litho_image_grad(

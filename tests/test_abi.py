@@ -28,15 +28,29 @@ def test_library_exports_every_header_symbol(clib):
     assert set(names) == set(A.SIGNATURES), set(names) ^ set(A.SIGNATURES)
 
 
+KINDS = {"annular": A.LITHO_SRC_ANNULAR, "dipole_x": A.LITHO_SRC_DIPOLE_X, "dipole_y": A.LITHO_SRC_DIPOLE_Y,
+         "points": A.LITHO_SRC_POINTS}
+
+
 def _optics(spec, K=None, focus=None):
     focus = tuple(spec.focus_nm if focus is None else focus)
     arr = (C.c_double * len(focus))(*focus)
+    flat = [float(v) for p in spec.points for v in p]
+    pts = (C.c_double * max(1, len(flat)))(*flat)
     o = A.Optics(n=spec.n, pixel_nm=spec.pixel_nm, wavelength_nm=spec.wavelength_nm, na=spec.na,
-                 source_kind=0 if spec.source == "annular" else 1, source_grid=spec.source_grid,
+                 source_kind=KINDS[spec.source], source_grid=spec.source_grid,
                  sigma_in=spec.sigma_in, sigma_out=spec.sigma_out, n_focus=len(focus),
-                 focus_nm=C.cast(arr, C.POINTER(C.c_double)), K=spec.K if K is None else K, dose=1.0)
-    o._keep = arr
+                 focus_nm=C.cast(arr, C.POINTER(C.c_double)), K=spec.K if K is None else K, dose=1.0,
+                 src_points=C.cast(pts, C.POINTER(C.c_double)) if flat else None,
+                 n_src_points=len(spec.points))
+    o._keep = (arr, pts)
     return o
+
+
+def _points_spec(spec):
+    # the lattice source of `spec` written out as an explicit point list (weights 2)
+    sx, sy, _ = O.source_points(spec)
+    return spec.with_(source="points", points=tuple((float(a), float(b), 2.0) for a, b in zip(sx, sy)))
 
 
 def test_host_argument_validation(clib):
@@ -77,7 +91,9 @@ def _host_socs(clib, spec, plane, K):
 
 
 @pytest.mark.parametrize("spec,plane", [(W.CONFIG1, 0), (W.fd_clip_optics(64), 0),
-                                        (W.fd_clip_optics(64), 2), (W.CONFIG2.with_(n=256), 0)])
+                                        (W.fd_clip_optics(64), 2), (W.CONFIG2.with_(n=256), 0),
+                                        (W.CONFIG2.with_(n=128, source="dipole_y"), 0),
+                                        (_points_spec(W.CONFIG1.with_(n=64)), 0)])
 def test_host_bank_matches_oracle(clib, spec, plane):
     K = 24 if spec.K > 8 else 8
     lam_c, phi_c = _host_socs(clib, spec, plane, K)
@@ -101,3 +117,17 @@ def test_host_bank_full_spectrum_sum_matches_trace(clib):
     assert abs(lam.sum() - lam_o.sum()) < 1e-10 * lam_o.sum()
     assert lam.min() > 0
     assert np.all(np.diff(lam) <= 1e-12 * lam[0])
+
+
+def test_point_source_validation(clib):
+    h = C.c_void_p()
+    bad = W.CONFIG1.with_(n=64, source="points", points=((1.2, 0.0, 1.0),))      # |sigma| > 1
+    assert clib.litho_kernels_build(C.byref(_optics(bad)), C.byref(h)) == A.LITHO_E_INVALID
+    bad = W.CONFIG1.with_(n=64, source="points", points=((0.5, 0.0, -1.0),))     # negative weight
+    assert clib.litho_kernels_build(C.byref(_optics(bad)), C.byref(h)) == A.LITHO_E_INVALID
+    o = _optics(W.CONFIG1.with_(n=64, source="points", points=((0.5, 0.0, 1.0),)))
+    o.src_points = None
+    assert clib.litho_kernels_build(C.byref(o), C.byref(h)) == A.LITHO_E_INVALID
+    o = _optics(W.CONFIG1.with_(n=64))
+    o.source_kind = 9
+    assert clib.litho_kernels_build(C.byref(o), C.byref(h)) == A.LITHO_E_INVALID

@@ -166,3 +166,19 @@ def test_through_focus_gradient_2048():
     assert abs(loss.item() - Lo) < 1e-5 * Lo
     assert rel_l2(g, go) < GTOL
     assert rel_l2(g[992:1056, 992:1056], go[992:1056, 992:1056]) < GTOL
+
+
+def test_plane_weighted_loss_and_gradient(L):
+    # through-focus loss with unequal plane weights against the oracle
+    spec = W.fd_clip_optics(128).with_(K=10)
+    bank = L.Bank.from_spec(spec)
+    m = W.as_f32_exact(W.curvilinear_mask(128, 41))
+    T = W.manhattan_target(128, 42)
+    wts = [0.5, 1.0, 2.0]
+    _, loss, grad = L.image_grad(bank, dev(m[None]), target=dev(T[None]), slope=SLOPE, threshold=THR,
+                                 want_image=False, plane_weights=wts)
+    Lo, go, _ = O.gradient(m, T, _banks(spec, 10), SLOPE, THR, weights=wts)
+    assert abs(loss.item() - Lo) < 1e-5 * Lo
+    assert rel_l2(grad.cpu().numpy()[0], go) < GTOL
+    with pytest.raises(ValueError):
+        L.image_grad(bank, dev(m[None]), target=dev(T[None]), plane_weights=[1.0])

@@ -157,3 +157,36 @@ def test_full_tile_4096_window(L):
         lam, phi = O.socs_kernels(spec, F, K=32)
         ref = O.image_window(mh, lam, phi, 4096, 1920, 1920, 256, 256)
         assert rel_l2(img[p][1920:2176, 1920:2176], ref) < TOL, p
+
+
+@pytest.mark.parametrize("source", ["dipole_y", "points"])
+def test_other_source_kinds_parity(L, source):
+    # y-dipole, and an explicit point list (the x-dipole lattice, unequal weights)
+    base = W.fd_clip_optics(128).with_(K=16, focus_nm=(0.0, 30.0))
+    if source == "points":
+        sx, sy, _ = O.source_points(base)
+        rng = np.random.default_rng(17)
+        spec = base.with_(source="points", points=tuple((float(a), float(b), float(w))
+                                                         for a, b, w in zip(sx, sy, rng.uniform(0.5, 2.0, sx.size))))
+    else:
+        spec = base.with_(source="dipole_y")
+    bank = L.Bank.from_spec(spec)
+    masks = np.stack([W.as_f32_exact(W.curvilinear_mask(128, 300 + s)) for s in range(2)])
+    img = L.image(bank, dev(masks)).cpu().numpy()
+    for p, F in enumerate(spec.focus_nm):
+        lam, phi = O.socs_kernels(spec, F, K=16)
+        for i in range(2):
+            assert rel_l2(img[i, p], O.image(masks[i], lam, phi)) < TOL, (p, i)
+
+
+def test_bank_info_clear_field_and_gap(L):
+    spec = W.CONFIG1
+    bank = L.Bank.from_spec(spec)
+    lam, phi = O.socs_kernels(spec, 0.0, K=9)
+    b = bank.b
+    cf = float(np.sum(lam[:8] * np.abs(phi[:8, b, b]) ** 2))
+    assert abs(bank.clear_field - cf) < 1e-12 * cf
+    assert abs(bank.degeneracy_gap - (lam[7] - lam[8]) / lam[0]) < 1e-9
+    # the clear-field image equals the reported value
+    img = L.image(bank, dev(np.ones((1, 128, 128)))).cpu().numpy()
+    assert abs(img.mean() - cf) < 1e-5 * cf
