@@ -370,9 +370,19 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf
   for (int i = 0; i < E; ++i) acc[i] = 0.f;
   const size_t kstride = size_t(g.nt) * Q * kC;
   const cf *yc = Y + size_t(clip) * g.K * kstride;
+  // pruned variant: the band row of kernel k + 1 (half the elements) is
+  // loaded while kernel k is transformed
+  cf nxt[E];
+  if (PR) load_band_row<Q, T, PR>(nxt, yc, y, t, g.b);
   for (int k = 0; k < g.K; ++k) {
     cf v[E];
-    load_band_row<Q, T, PR>(v, yc + k * kstride, y, t, g.b);
+    if (PR) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = nxt[i];
+      if (k + 1 < g.K) load_band_row<Q, T, PR>(nxt, yc + (k + 1) * kstride, y, t, g.b);
+    } else {
+      load_band_row<Q, T, PR>(v, yc + k * kstride, y, t, g.b);
+    }
     fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) acc[i] += cabs2(v[i]);
@@ -402,7 +412,7 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf
 // GIN 0: G is a real [Q][Q] array per clip (Q == N), rows strided by Q.
 // GIN 1: G is a band [ntD][Q][kC] (|gx| <= 2b) per clip; its row is synthesised.
 template <int Q, int GIN, bool PR>
-__global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Greal,
+__global__ __launch_bounds__(256, (PR && RowWaves<Q>::value > 3) ? 3 : RowWaves<Q>::value) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Greal,
                                                     size_t g_clip_stride, const cf *__restrict__ Gband, Geo g,
                                                     const cf *__restrict__ tw) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
@@ -424,9 +434,20 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_adj(cf *__re
   }
   const size_t kstride = size_t(g.nt) * Q * kC;
   cf *yc = Y + size_t(clip) * g.K * kstride;
+  // pruned variant: the band row of kernel k + 1 (half the elements) is
+  // loaded while kernel k is transformed (each row is read completely before
+  // this wavefront overwrites it)
+  cf nxt[E];
+  if (PR) load_band_row<Q, T, PR>(nxt, yc, y, t, g.b);
   for (int k = 0; k < g.K; ++k) {
     cf v[E];
-    load_band_row<Q, T, PR>(v, yc + k * kstride, y, t, g.b);
+    if (PR) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = nxt[i];
+      if (k + 1 < g.K) load_band_row<Q, T, PR>(nxt, yc + (k + 1) * kstride, y, t, g.b);
+    } else {
+      load_band_row<Q, T, PR>(v, yc + k * kstride, y, t, g.b);
+    }
     fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = cscale(v[i], gr[i]);

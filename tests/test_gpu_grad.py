@@ -182,3 +182,21 @@ def test_plane_weighted_loss_and_gradient(L):
     assert rel_l2(grad.cpu().numpy()[0], go) < GTOL
     with pytest.raises(ValueError):
         L.image_grad(bank, dev(m[None]), target=dev(T[None]), plane_weights=[1.0])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_workspace_chunking_matches_single_pass(L, prec, monkeypatch):
+    # a workspace limit below one clip forces one clip per chunk: results must
+    # equal the single-pass call bit for bit (per-clip work does not depend on
+    # the chunking)
+    import torch
+    spec = W.fd_clip_optics(256).with_(K=8)
+    bank = L.Bank.from_spec(spec)
+    masks = np.stack([W.as_f32_exact(W.curvilinear_mask(256, 60 + s)) for s in range(5)])
+    tgts = np.stack([W.manhattan_target(256, 70 + s) for s in range(5)])
+    img1, loss1, grad1 = L.image_grad(bank, dev(masks), target=dev(tgts), slope=SLOPE, threshold=THR, prec=prec)
+    monkeypatch.setenv("LITHO_WORKSPACE_MB", "1")
+    img2, loss2, grad2 = L.image_grad(bank, dev(masks), target=dev(tgts), slope=SLOPE, threshold=THR, prec=prec)
+    only = L.image(bank, dev(masks), prec=prec)
+    assert torch.equal(img1, img2) and torch.equal(grad1, grad2) and torch.equal(loss1, loss2)
+    assert torch.equal(only, img1)
