@@ -476,12 +476,28 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *_
 #pragma unroll
   for (int i = 0; i < E; ++i) acc[i] = cmake(0.f, 0.f);
   const int k0 = kc * g.kper, k1 = min(g.K, k0 + g.kper);
-  for (int k = k0; k < k1; ++k) {
-    const cf *src = V + ((size_t(clip) * g.K + k) * g.nt + jt) * size_t(Q) * kC + c;
+  const cf *vcol = V + ((size_t(clip) * g.K + k0) * g.nt + jt) * size_t(Q) * kC + c;
+  const size_t kstride = size_t(g.nt) * Q * kC;
+  // small transforms (pruned, at most 20 values per thread): the column of
+  // kernel k + 1 is loaded while kernel k is transformed
+  constexpr bool PF = PR && E <= 20 && T <= 32;
+  auto load_col = [&](cf (&dst)[E], int k) {
+    const cf *src = vcol + (k - k0) * kstride;
     const int tt = opaque_lane(t);
-    cf v[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = src[(tt + T * i) * kC];
+    for (int i = 0; i < E; ++i) dst[i] = src[(tt + T * i) * kC];
+  };
+  cf nxt[E];
+  if (PF) load_col(nxt, k0);
+  for (int k = k0; k < k1; ++k) {
+    cf v[E];
+    if (PF) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = nxt[i];
+      if (k + 1 < k1) load_col(nxt, k + 1);
+    } else {
+      load_col(v, k);
+    }
     fft<Q, -1>(v, buf, t, tw);
     const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + jt) * g.B * kC + c;
     const int t2 = opaque_lane(t);
