@@ -29,7 +29,7 @@
  *   - A bank owns device memory (kernels, FFT tables, workspaces) until
  *     litho_kernels_free().  Calls on different streams get separate
  *     workspaces; calls on one stream are ordered by the stream.
- *   - Grid sides n must be powers of two with 64 <= n <= 4096
+ *   - Grid sides n must be 2^j, 3*2^j or 5*2^j with 64 <= n <= 4096
  *     (LITHO_E_UNSUPPORTED otherwise).
  */
 #ifndef LITHO_H

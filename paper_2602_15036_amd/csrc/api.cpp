@@ -76,12 +76,13 @@ void prof_end(const char *name, hipStream_t s) {
 }
 
 // ============================================================ geometry helpers
-bool pow2_side(int n) { return n >= 64 && n <= 4096 && (n & (n - 1)) == 0; }
+// Clip sides with an FFT plan: 2^j {1, 3, 5}, 64 <= n <= 4096.
+bool supported_side(int n) { return pass_threads(n) != 0; }
 
 // Smallest supported side >= 4b + 1 below n (exact for |E_k|^2, which is
 // band-limited to |f| <= 2b), else n itself.
 int auto_inner_grid(int n, int b) {
-  static const int sizes[] = {64, 96, 128, 160, 256, 320, 512, 640, 768, 1024, 1280, 1536, 2048, 2560, 3072};
+  static const int sizes[] = {64, 96, 128, 160, 192, 256, 320, 384, 512, 640, 768, 1024, 1280, 1536, 2048, 2560, 3072};
   for (int q : sizes)
     if (q >= 4 * b + 1 && q < n) return q;
   return n;
@@ -209,8 +210,8 @@ extern "C" int litho_kernels_build(const litho_optics_t *optics, litho_bank_t **
     return LITHO_E_INVALID;
   }
   *out = nullptr;
-  if (!pow2_side(optics->n)) {
-    set_error("litho_kernels_build: grid side %d is not a power of two in [64, 4096]", optics->n);
+  if (!supported_side(optics->n)) {
+    set_error("litho_kernels_build: grid side %d is not 2^j times 1, 3 or 5 in [64, 4096]", optics->n);
     return LITHO_E_UNSUPPORTED;
   }
   auto *bk = new litho_bank();
@@ -232,8 +233,8 @@ extern "C" int litho_kernels_load(int n, int B, int K, int n_focus, const double
     return LITHO_E_INVALID;
   }
   *out = nullptr;
-  if (!pow2_side(n)) {
-    set_error("litho_kernels_load: grid side %d is not a power of two in [64, 4096]", n);
+  if (!supported_side(n)) {
+    set_error("litho_kernels_load: grid side %d is not 2^j times 1, 3 or 5 in [64, 4096]", n);
     return LITHO_E_UNSUPPORTED;
   }
   if (B < 1 || (B % 2) == 0 || B > n || K < 1 || n_focus < 1 || n_focus > 8) {
@@ -396,7 +397,7 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
   const bool resample = g.Q != g.N;
   // loss partials come from the row pass that applies the resist (N grid):
   // one per block; with resampling that pass takes two rows per transform
-  L.nblk = g.N / (256 / pass_threads(g.N)) / (resample ? 2 : 1);
+  L.nblk = resample ? (g.N / (256 / pass_threads(g.N)) + 1) / 2 : g.N / (256 / pass_threads(g.N));
   const size_t N = g.N, Q = g.Q;
   L.b_S1 = align256(size_t(g.nt) * N * kTileCols * sizeof(float2));
   L.b_Mh = align256(size_t(g.nt) * g.B * kTileCols * sizeof(float2));

@@ -253,7 +253,9 @@ template <> struct FftPlan<2048> { static constexpr int T = 64; using R = Radice
 template <> struct FftPlan<4096> { static constexpr int T = 128; using R = Radices<16, 16, 16>; };
 template <> struct FftPlan<96> { static constexpr int T = 8; using R = Radices<4, 2, 12>; };
 template <> struct FftPlan<160> { static constexpr int T = 8; using R = Radices<4, 4, 10>; };
+template <> struct FftPlan<192> { static constexpr int T = 16; using R = Radices<4, 4, 12>; };
 template <> struct FftPlan<320> { static constexpr int T = 16; using R = Radices<4, 4, 20>; };
+template <> struct FftPlan<384> { static constexpr int T = 16; using R = Radices<4, 8, 12>; };
 template <> struct FftPlan<640> { static constexpr int T = 32; using R = Radices<4, 4, 4, 10>; };
 template <> struct FftPlan<768> { static constexpr int T = 32; using R = Radices<8, 8, 12>; };
 template <> struct FftPlan<1280> { static constexpr int T = 64; using R = Radices<4, 4, 4, 20>; };

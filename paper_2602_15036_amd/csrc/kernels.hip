@@ -187,7 +187,11 @@ __global__ __launch_bounds__(256) void k_rows_fwd_real(const float *__restrict__
   constexpr int T = FftPlan<L>::T, E = L / T, RPB = 256 / T;
   extern __shared__ cf smem[];
   const int row = threadIdx.x / T, t = threadIdx.x % T;
-  const int y0 = 2 * (blockIdx.x * RPB + row), clip = blockIdx.y;
+  // rows y0, y0 + 1; a block past the last pair (L / RPB odd) recomputes the
+  // last pair and stores nothing
+  const int yp = 2 * (blockIdx.x * RPB + row), clip = blockIdx.y;
+  const bool store = yp < L;
+  const int y0 = store ? yp : L - 2;
   const float *src = in + clip * in_clip + size_t(y0) * L;
   cf *buf = smem + row * lds_len<L>();
   cf v[E];
@@ -200,10 +204,12 @@ __global__ __launch_bounds__(256) void k_rows_fwd_real(const float *__restrict__
   cf w[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const cf a = v[i], b = buf[(L - t - T * i) & (L - 1)];
+    const int p = t + T * i;
+    const cf a = v[i], b = buf[p == 0 ? 0 : L - p];
     v[i] = cmake(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
     w[i] = cmake(0.5f * (a.y + b.y), 0.5f * (b.x - a.x));
   }
+  if (!store) return;
   cf *dst = out + size_t(clip) * (Wp / kC) * L * kC;
   store_band_row<L, T>(v, dst, y0, t, h, Wp, scale);
   store_band_row<L, T>(w, dst, y0 + 1, t, h, Wp, scale);
@@ -233,7 +239,10 @@ __global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in
 #pragma unroll
     for (int i = 0; i < E; ++i) dst[t + T * i] = scale * v[i].x;
   } else {
-    const int y0 = 2 * (blockIdx.x * RPB + row);
+    // a block past the last pair (L / RPB odd) recomputes it and stores nothing
+    const int yp = 2 * (blockIdx.x * RPB + row);
+    const bool store = yp < L;
+    const int y0 = store ? yp : L - 2;
     cf b[E];
     load_band_row<L, T>(v, src, y0, t, h);
     load_band_row<L, T>(b, src, y0 + 1, t, h);
@@ -241,10 +250,12 @@ __global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in
     for (int i = 0; i < E; ++i) v[i] = cmake(v[i].x - b[i].y, v[i].y + b[i].x);
     fft<L, +1>(v, smem + row * lds_len<L>(), t, tw);
     double lsum = 0.0;
+    if (store) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      lsum += image_epilogue(ep, g, clip, y0, t + T * i, scale * v[i].x);
-      lsum += image_epilogue(ep, g, clip, y0 + 1, t + T * i, scale * v[i].y);
+      for (int i = 0; i < E; ++i) {
+        lsum += image_epilogue(ep, g, clip, y0, t + T * i, scale * v[i].x);
+        lsum += image_epilogue(ep, g, clip, y0 + 1, t + T * i, scale * v[i].y);
+      }
     }
     if (ep.target) {
       const double s = block_sum(lsum, reinterpret_cast<double *>(smem));
@@ -1018,7 +1029,7 @@ int rows_fwd_real_l(const char *name, const float *in, size_t in_clip, cf *out, 
                     float scale, int nclips, hipStream_t s) {
   constexpr int T = FftPlan<L>::T, RPB = 256 / T;
   size_t sh = size_t(RPB) * lds_len<L>() * sizeof(cf);
-  const dim3 grid(L / RPB / 2, nclips);  // two rows per transform
+  const dim3 grid((L / RPB + 1) / 2, nclips);  // two rows per transform
   return launch(name, KPTR(dev::k_rows_fwd_real<L>), grid, sh, s, [&] {
     hipLaunchKernelGGL(dev::k_rows_fwd_real<L>, grid, dim3(256), sh, s, in, in_clip, out, h, Wp, tw, scale);
   });
@@ -1032,7 +1043,7 @@ int rows_inv_real_l(const char *name, const cf *in, int h, int Wp, float *out, c
   sh = std::max(sh, size_t(256) * sizeof(double));
   Geo g = to_geo(pg);
   Epi e = to_epi(ep);
-  const dim3 grid(L / RPB / (MODE == 1 ? 2 : 1), nclips);  // MODE 1: two rows per transform
+  const dim3 grid(MODE == 1 ? (L / RPB + 1) / 2 : L / RPB, nclips);  // MODE 1: two rows per transform
   return launch(name, KPTR(dev::k_rows_inv_real<L, MODE>), grid, sh, s, [&] {
     hipLaunchKernelGGL((dev::k_rows_inv_real<L, MODE>), grid, dim3(256), sh, s, in, h, Wp, out, e, g, tw, scale);
   });
@@ -1275,49 +1286,32 @@ void fill_adj_table_e(int Q, int b, std::vector<uint16_t> &out) {
 
 }  // namespace
 
+// Every transform length with an FFT plan (2^j, 3 * 2^j, 5 * 2^j): clip sides
+// and inner grids alike.  All length switches below expand this one list.
+#define LITHO_FFT_SIZES(X, A)                                                                       \
+  X(64, A) X(96, A) X(128, A) X(160, A) X(192, A) X(256, A) X(320, A) X(384, A) X(512, A) X(640, A) \
+  X(768, A) X(1024, A) X(1280, A) X(1536, A) X(2048, A) X(2560, A) X(3072, A) X(4096, A)
+
 #define LITHO_CASE(L, CALL) \
   case L: {                 \
     constexpr int NN = L;   \
     return CALL;            \
   }
 
-// Grid sides (masks, outputs): powers of two.
-#define LITHO_DISPATCH_N(n, CALL)                        \
-  switch (n) {                                           \
-    LITHO_CASE(64, CALL)                                 \
-    LITHO_CASE(128, CALL)                                \
-    LITHO_CASE(256, CALL)                                \
-    LITHO_CASE(512, CALL)                                \
-    LITHO_CASE(1024, CALL)                               \
-    LITHO_CASE(2048, CALL)                               \
-    LITHO_CASE(4096, CALL)                               \
-    default:                                             \
-      set_error("unsupported grid side %d", n);          \
-      return LITHO_E_UNSUPPORTED;                        \
+#define LITHO_DISPATCH_N(n, CALL)                   \
+  switch (n) {                                      \
+    LITHO_FFT_SIZES(LITHO_CASE, CALL)               \
+    default:                                        \
+      set_error("unsupported grid side %d", n);     \
+      return LITHO_E_UNSUPPORTED;                   \
   }
 
-// Per-kernel grid sides: powers of two and 3 or 5 times a power of two.
-#define LITHO_DISPATCH_Q(q, CALL)                        \
-  switch (q) {                                           \
-    LITHO_CASE(64, CALL)                                 \
-    LITHO_CASE(96, CALL)                                 \
-    LITHO_CASE(128, CALL)                                \
-    LITHO_CASE(160, CALL)                                \
-    LITHO_CASE(256, CALL)                                \
-    LITHO_CASE(320, CALL)                                \
-    LITHO_CASE(512, CALL)                                \
-    LITHO_CASE(640, CALL)                                \
-    LITHO_CASE(768, CALL)                                \
-    LITHO_CASE(1024, CALL)                               \
-    LITHO_CASE(1280, CALL)                               \
-    LITHO_CASE(1536, CALL)                               \
-    LITHO_CASE(2048, CALL)                               \
-    LITHO_CASE(2560, CALL)                               \
-    LITHO_CASE(3072, CALL)                               \
-    LITHO_CASE(4096, CALL)                               \
-    default:                                             \
-      set_error("unsupported inner grid side %d", q);    \
-      return LITHO_E_UNSUPPORTED;                        \
+#define LITHO_DISPATCH_Q(q, CALL)                   \
+  switch (q) {                                      \
+    LITHO_FFT_SIZES(LITHO_CASE, CALL)               \
+    default:                                        \
+      set_error("unsupported inner grid side %d", q); \
+      return LITHO_E_UNSUPPORTED;                   \
   }
 
 int run_rows_fwd_real(const char *name, int L, const float *in, size_t in_clip, cf2 *out, int h, int Wp,
@@ -1412,14 +1406,12 @@ void fill_band_table(int Q, int b, bool bf16, std::vector<uint16_t> &out) {
 
 int twiddle_table(int L, std::vector<float2> &out) {
   switch (L) {
-#define LITHO_TW(X)                                      \
-  case X:                                                \
+#define LITHO_TW(X, _)                                                            \
+  case X:                                                                         \
     out.assign(std::max(1, dev::twiddle_table_size<X>()), make_float2(0.f, 0.f)); \
-    dev::fill_twiddles<X>(out.data());                   \
+    dev::fill_twiddles<X>(out.data());                                            \
     return LITHO_OK;
-    LITHO_TW(64) LITHO_TW(96) LITHO_TW(128) LITHO_TW(160) LITHO_TW(256) LITHO_TW(320) LITHO_TW(512) LITHO_TW(640)
-    LITHO_TW(768) LITHO_TW(1024) LITHO_TW(1280) LITHO_TW(1536) LITHO_TW(2048) LITHO_TW(2560) LITHO_TW(3072)
-    LITHO_TW(4096)
+    LITHO_FFT_SIZES(LITHO_TW, 0)
 #undef LITHO_TW
     default:
       set_error("no FFT plan for length %d", L);
@@ -1429,12 +1421,10 @@ int twiddle_table(int L, std::vector<float2> &out) {
 
 int pass_threads(int L) {
   switch (L) {
-#define LITHO_T(X) \
-  case X:          \
+#define LITHO_T(X, _) \
+  case X:             \
     return FftPlan<X>::T;
-    LITHO_T(64) LITHO_T(96) LITHO_T(128) LITHO_T(160) LITHO_T(256) LITHO_T(320) LITHO_T(512) LITHO_T(640)
-    LITHO_T(768) LITHO_T(1024) LITHO_T(1280) LITHO_T(1536) LITHO_T(2048) LITHO_T(2560) LITHO_T(3072)
-    LITHO_T(4096)
+    LITHO_FFT_SIZES(LITHO_T, 0)
 #undef LITHO_T
     default: return 0;
   }

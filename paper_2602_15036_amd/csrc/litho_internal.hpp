@@ -26,7 +26,7 @@ struct CallLayout {
 };
 
 size_t workspace_limit_bytes();
-bool pow2_side(int n);
+bool supported_side(int n);
 
 }  // namespace litho
 

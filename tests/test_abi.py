@@ -131,3 +131,10 @@ def test_point_source_validation(clib):
     o = _optics(W.CONFIG1.with_(n=64))
     o.source_kind = 9
     assert clib.litho_kernels_build(C.byref(o), C.byref(h)) == A.LITHO_E_INVALID
+
+
+def test_clip_side_validation(clib):
+    h = C.c_void_p()
+    for n in (100, 448, 8192, 48):     # 7 * 64, beyond 4096, below 64
+        o = _optics(W.CONFIG1.with_(n=n))
+        assert clib.litho_kernels_build(C.byref(o), C.byref(h)) == A.LITHO_E_UNSUPPORTED, n

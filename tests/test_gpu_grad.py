@@ -200,3 +200,20 @@ def test_workspace_chunking_matches_single_pass(L, prec, monkeypatch):
     only = L.image(bank, dev(masks), prec=prec)
     assert torch.equal(img1, img2) and torch.equal(grad1, grad2) and torch.equal(loss1, loss2)
     assert torch.equal(only, img1)
+
+
+@pytest.mark.parametrize("n,inner", [(96, 0), (96, 96), (192, 0), (320, 0), (384, 384), (640, 0)])
+def test_clip_sides_with_factors_three_and_five(L, n, inner):
+    # clip sides 3 * 2^j and 5 * 2^j, resampled (inner 0) and on the full grid
+    spec = W.fd_clip_optics(n).with_(K=8)
+    bank = L.Bank.from_spec(spec)
+    bank.set_inner_grid(inner)
+    assert bank.inner_grid != n or inner == n
+    m = W.as_f32_exact(W.curvilinear_mask(n, 90 + n))
+    T = W.manhattan_target(n, 91 + n)
+    img, loss, grad = L.image_grad(bank, dev(m[None]), target=dev(T[None]), slope=SLOPE, threshold=THR)
+    Lo, go, imgs = O.gradient(m, T, _banks(spec, 8), SLOPE, THR, method="fft")
+    for p in range(3):
+        assert rel_l2(img.cpu().numpy()[0, p], imgs[p]) < 1e-5, p
+    assert abs(loss.item() - Lo) < 1e-5 * Lo
+    assert rel_l2(grad.cpu().numpy()[0], go) < GTOL
