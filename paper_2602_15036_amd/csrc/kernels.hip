@@ -326,35 +326,51 @@ __global__ __launch_bounds__(ColBlock<L>::threads) void k_col_fft(const cf *__re
 }
 
 // ------------------------------------------------------------ forward column pass
-// Y_k[jt][y][c] = sum_ky Phi'_k(ky, j) Mh(ky, j) exp(+2 pi i ky y / Q).
+// Y_k[jt][y][c] = sum_ky Phi'_k(ky, j) Mh(ky, j) exp(+2 pi i ky y / Q), for the
+// kernels k0 .. k0 + kpb - 1 of this block: the mask-spectrum column stays in
+// registers and the next kernel's column is loaded while one is transformed.
 template <int Q, bool PR>
 __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_fwd(const cf *__restrict__ bank,
                                                                     const cf *__restrict__ Mh, cf *__restrict__ Y,
-                                                                    Geo g, const cf *__restrict__ tw) {
+                                                                    Geo g, const cf *__restrict__ tw, int kpb) {
   constexpr int T = FftPlan<Q>::T, E = Q / T;
   extern __shared__ cf smem[];
   int jt, c, t;
   bool valid;
   col_coords<Q>(g.nt, jt, c, t, valid);
-  const int k = blockIdx.y, clip = blockIdx.z;
+  const int k0 = blockIdx.y * kpb, k1 = min(g.K, k0 + kpb), clip = blockIdx.z;
   cf *buf = smem + (threadIdx.x / T) * lds_len<Q>();
-  const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + jt) * g.B * kC + c;
+  const size_t kb = size_t(g.nt) * g.B * kC;
+  const cf *ph = bank + (size_t(g.p) * g.Kbank * g.nt + jt) * g.B * kC + c;
   const cf *mh = Mh + (size_t(clip) * g.nt + jt) * g.B * kC + c;
-  cf v[E];
+  auto load_band = [&](cf (&dst)[E], const cf *col) {
+    const int tt = opaque_lane(t);
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    if (PR && never_in_band<Q>(i)) {
-      v[i] = cmake(0.f, 0.f);
-      continue;
+    for (int i = 0; i < E; ++i) {
+      if (PR && never_in_band<Q>(i)) {
+        dst[i] = cmake(0.f, 0.f);
+        continue;
+      }
+      const int r = band_row_of(tt + T * i, Q, g.b);
+      dst[i] = r >= 0 ? col[r * kC] : cmake(0.f, 0.f);
     }
-    const int r = band_row_of(t + T * i, Q, g.b);
-    v[i] = r >= 0 ? cmul(ph[r * kC], mh[r * kC]) : cmake(0.f, 0.f);
-  }
-  fft<Q, +1>(v, buf, t, tw);
-  if (!valid) return;
-  cf *dst = Y + ((size_t(clip) * g.K + k) * g.nt + jt) * size_t(Q) * kC + c;
+  };
+  cf m[E], nxt[E];
+  load_band(m, mh);
+  load_band(nxt, ph + k0 * kb);
+  for (int k = k0; k < k1; ++k) {
+    cf v[E];
 #pragma unroll
-  for (int i = 0; i < E; ++i) dst[(t + T * i) * kC] = v[i];
+    for (int i = 0; i < E; ++i) v[i] = cmul(nxt[i], m[i]);
+    if (k + 1 < k1) load_band(nxt, ph + (k + 1) * kb);
+    fft<Q, +1>(v, buf, t, tw);
+    if (valid) {
+      cf *dst = Y + ((size_t(clip) * g.K + k) * g.nt + jt) * size_t(Q) * kC + c;
+      const int tt = opaque_lane(t);
+#pragma unroll
+      for (int i = 0; i < E; ++i) dst[(tt + T * i) * kC] = v[i];
+    }
+  }
 }
 
 // Occupancy target of the k-loop row passes: four wavefronts per SIMD (128
@@ -1075,15 +1091,20 @@ int pass_y_fwd_q(const cf *bank, const cf *Mh, cf *Y, const PassGeo &pg, const c
                  hipStream_t s) {
   Geo g = to_geo(pg);
   constexpr size_t sh = col_lds<Q>();
-  const dim3 grid(col_blocks<Q>(g.nt), g.K, nclips);
+  // kernels per block: enough blocks to fill the device (~2560), the rest
+  // looped inside a block
+  const int per_k = col_blocks<Q>(g.nt) * nclips;
+  const int groups = std::max(1, std::min(g.K, (2560 + per_k - 1) / per_k));
+  const int kpb = (g.K + groups - 1) / groups;
+  const dim3 grid(col_blocks<Q>(g.nt), (g.K + kpb - 1) / kpb, nclips);
   if (dev::prunable<Q>(g.b))
     return launch("pass_y_fwd", KPTR(dev::k_pass_y_fwd<Q, true>), grid, sh, s, [&] {
       hipLaunchKernelGGL((dev::k_pass_y_fwd<Q, true>), grid, dim3(dev::ColBlock<Q>::threads), sh, s, bank, Mh, Y, g,
-                         twQ);
+                         twQ, kpb);
     });
   return launch("pass_y_fwd", KPTR(dev::k_pass_y_fwd<Q, false>), grid, sh, s, [&] {
     hipLaunchKernelGGL((dev::k_pass_y_fwd<Q, false>), grid, dim3(dev::ColBlock<Q>::threads), sh, s, bank, Mh, Y, g,
-                       twQ);
+                       twQ, kpb);
   });
 }
 
