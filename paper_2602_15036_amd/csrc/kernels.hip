@@ -525,17 +525,25 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *_
     } else {
       load_col(v, k);
     }
+    // conj(Phi'_k) at this thread's band rows, loaded before the transform
+    // so that it hides their latency (zero off the band)
+    cf w[E];
+    {
+      const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + jt) * g.B * kC + c;
+      const int t2 = opaque_lane(t);
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        w[i] = cmake(0.f, 0.f);
+        if (PR && never_in_band<Q>(i)) continue;
+        const int r = band_row_of(t2 + T * i, Q, g.b);
+        if (r >= 0) w[i] = ph[r * kC];
+      }
+    }
     fft<Q, -1>(v, buf, t, tw);
-    const cf *ph = bank + ((size_t(g.p) * g.Kbank + k) * g.nt + jt) * g.B * kC + c;
-    const int t2 = opaque_lane(t);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       if (PR && never_in_band<Q>(i)) continue;
-      const int r = band_row_of(t2 + T * i, Q, g.b);
-      if (r >= 0) {
-        const cf w = ph[r * kC];
-        acc[i] = make_float2(acc[i].x + w.x * v[i].x + w.y * v[i].y, acc[i].y + w.x * v[i].y - w.y * v[i].x);
-      }
+      acc[i] = make_float2(acc[i].x + w[i].x * v[i].x + w[i].y * v[i].y, acc[i].y + w[i].x * v[i].y - w[i].y * v[i].x);
     }
   }
   if (!valid) return;
