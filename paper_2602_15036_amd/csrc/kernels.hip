@@ -599,7 +599,8 @@ __global__ __launch_bounds__(ColBlock<N>::threads) void k_grad_cols(const double
 //   Y_k^T[kx][y] = sum_ky X_k^T[kx][ky] W[ky][y],  X_k = Phi'_k * Mh,  W[ky][y] = exp(+2 pi i (ky - b) y / Q)
 // with v_mfma_f32_32x32x16_{f16,bf16} and FP32 accumulation.  SPLIT operands are
 // x = hi + lo (hi = round(x), lo = round(x - hi)) and the product keeps
-// hi*hi + hi*lo + lo*hi.  One wavefront computes a 32 (kx) x 128 (y) tile.
+// hi*hi + hi*lo + lo*hi.  A workgroup of four waves computes a 32 (kx) x 256 (y)
+// tile, each wave 32 x 64.
 // Operand layout of the 32x32x16 instruction: lane l holds A[l % 32][8 (l / 32) + j]
 // and B[8 (l / 32) + j][l % 32], j = 0..7; accumulator register i of lane l holds
 // D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
@@ -625,8 +626,9 @@ struct Mfma<__bf16> {
   }
 };
 
-// N-tiles (32 wide) per wave of the GEMM kernels; the waves per workgroup (NW)
-// are a template parameter, 4 or 5, chosen so that the N extent splits evenly.
+// N-tiles (32 wide) per wave of the forward GEMM kernel (the adjoint one uses
+// one); the waves per workgroup (NW) are a template parameter: 4 for the
+// forward GEMM, 4 or 10 for the adjoint one.
 constexpr int kGemmNtw = 2;
 
 // A-operand fragments of one K-step (32 x 16) in LDS, in the instruction's
@@ -1208,8 +1210,6 @@ int pass_y_fwd_mfma_nw(const cf *bank, const cf *Mh, cf *Y, const Geo &g, const 
   });
 }
 
-// Five waves when the 32-wide N-tiles split evenly into groups of ten.
-inline bool five_waves(int tiles) { return tiles > 8 && tiles % 10 == 0; }
 // Waves of the adjoint GEMM workgroup: ten when the 32-row ky tiles come in
 // groups of ten, else four.
 inline int adj_gemm_waves(int B) { return (B + 31) / 32 % 10 == 0 ? 10 : 4; }
@@ -1222,12 +1222,9 @@ int pass_y_fwd_mfma_e(const cf *bank, const cf *Mh, cf *Y, const PassGeo &pg, co
     set_error("pass_y_fwd_mfma: inner grid %d is not a multiple of 32", g.Q);
     return LITHO_E_UNSUPPORTED;
   }
-  const bool five = false;
-  if (split)
-    return five ? pass_y_fwd_mfma_nw<E, true, 5>(bank, Mh, Y, g, tab, sin, nclips, s)
-                : pass_y_fwd_mfma_nw<E, true, 4>(bank, Mh, Y, g, tab, sin, nclips, s);
-  return five ? pass_y_fwd_mfma_nw<E, false, 5>(bank, Mh, Y, g, tab, sin, nclips, s)
-              : pass_y_fwd_mfma_nw<E, false, 4>(bank, Mh, Y, g, tab, sin, nclips, s);
+  // four waves per workgroup: two workgroups fit a CU at these register counts
+  if (split) return pass_y_fwd_mfma_nw<E, true, 4>(bank, Mh, Y, g, tab, sin, nclips, s);
+  return pass_y_fwd_mfma_nw<E, false, 4>(bank, Mh, Y, g, tab, sin, nclips, s);
 }
 
 template <typename E>

@@ -225,17 +225,17 @@ class LithoImage(torch.autograd.Function):
     """I = SOCS image of the mask; backward is the adjoint with dL/dI (E_k recomputed)."""
 
     @staticmethod
-    def forward(ctx, mask, bank: Bank, K_use: Optional[int] = None):
-        ctx.bank, ctx.K_use = bank, K_use
+    def forward(ctx, mask, bank: Bank, K_use: Optional[int] = None, prec="fp32"):
+        ctx.bank, ctx.K_use, ctx.prec = bank, K_use, prec
         ctx.save_for_backward(mask)
-        return image(bank, mask.contiguous(), K_use)
+        return image(bank, mask.contiguous(), K_use, prec=prec)
 
     @staticmethod
     def backward(ctx, g_image):
         (mask,) = ctx.saved_tensors
         _, _, g = image_grad(ctx.bank, mask.contiguous(), grad_image=g_image.contiguous().float(),
-                             K_use=ctx.K_use, want_image=False)
-        return g.view_as(mask), None, None
+                             K_use=ctx.K_use, want_image=False, prec=ctx.prec)
+        return g.view_as(mask), None, None, None
 
 
 class LithoILTLoss(torch.autograd.Function):
@@ -247,9 +247,10 @@ class LithoILTLoss(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, mask, target, bank: Bank, K_use: Optional[int] = None, slope: float = 50.0,
-                threshold: float = 0.3):
+                threshold: float = 0.3, prec="fp32", plane_weights: Optional[Sequence[float]] = None):
         _, loss, grad = image_grad(bank, mask.contiguous(), target=target.contiguous(), slope=slope,
-                                   threshold=threshold, K_use=K_use, want_image=False)
+                                   threshold=threshold, K_use=K_use, want_image=False, prec=prec,
+                                   plane_weights=plane_weights)
         ctx.save_for_backward(grad)
         ctx.mask_shape = mask.shape
         return loss
@@ -258,7 +259,7 @@ class LithoILTLoss(torch.autograd.Function):
     def backward(ctx, g_loss):
         (grad,) = ctx.saved_tensors
         w = g_loss.to(torch.float32).view(-1, 1, 1)
-        return (grad * w).view(ctx.mask_shape), None, None, None, None, None
+        return (grad * w).view(ctx.mask_shape), None, None, None, None, None, None, None
 
 
 def profile_enable(on: bool = True) -> None:

@@ -103,6 +103,29 @@ def test_autograd_functions(L, clip64):
     assert rel_l2(m2.grad[1].cpu().numpy(), 2.0 * g1) < GTOL
 
 
+def test_autograd_functions_precision_and_plane_weights(L, clip64):
+    # the wrappers pass the precision mode and plane weights through to the
+    # library: f16x3 keeps FP32-level agreement with the oracle
+    import torch
+    spec, masks, targets, banks = clip64
+    bank = L.Bank.from_spec(spec)
+    pw = [0.5, 1.0, 2.0]
+    m = dev(masks).requires_grad_(True)
+    loss = L.LithoILTLoss.apply(m, dev(targets), bank, None, SLOPE, THR, "f16x3", pw)
+    loss.sum().backward()
+    for i in range(2):
+        Lo, go, _ = O.gradient(masks[i], targets[i], banks, SLOPE, THR, weights=pw)
+        assert abs(loss[i].item() - Lo) < 1e-5 * Lo
+        assert rel_l2(m.grad[i].cpu().numpy(), go) < GTOL
+    m2 = dev(masks).requires_grad_(True)
+    img = L.LithoImage.apply(m2, bank, None, "f16x3")
+    w = torch.linspace(-1, 1, img.numel(), device="cuda").view_as(img)
+    (img * w).sum().backward()
+    _, go, _ = O.gradient(masks[0], None, banks, SLOPE, THR,
+                          G_override=[w[0, p].double().cpu().numpy() for p in range(3)])
+    assert rel_l2(m2.grad[0].cpu().numpy(), go) < GTOL
+
+
 @pytest.mark.parametrize("n,inner", [(128, 0), (256, 0), (256, 256), (512, 0)])
 def test_gradient_parity_mid_sizes(L, n, inner):
     spec = W.fd_clip_optics(n).with_(K=12)
