@@ -145,6 +145,104 @@ __device__ __forceinline__ void store_band_row(const cf (&v)[L / T], cf *__restr
   for (unsigned j = W + t; j < unsigned(Wp); j += T) row[(j >> 2) * unsigned(L * kC) + (j & 3)] = cmake(0.f, 0.f);
 }
 
+// Raw buffer view of the uniform byte range [base, base + bytes).  Buffer
+// range checking makes a load at an offset at or beyond `bytes` return zero
+// and drops a store there, so positions off the band need neither a branch
+// nor an address of their own.
+constexpr unsigned kOffBand = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_view(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, int(bytes), 0x00020000);
+}
+// (whole-vector bit casts: a cast of one element of the loaded vector reads
+// element 0 with this compiler)
+using f2v = float __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cf buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  const f2v f = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, int(off), 0, 0));
+  return cmake(f.x, f.y);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, cf v) {
+  using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  f2v f;
+  f.x = v.x;
+  f.y = v.y;
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, f), r, int(off), 0, 0);
+}
+
+// Byte offsets of the band row |f| <= h of row y of a tiled array
+// [tiles][L][kC] in the FFT register layout (thread t holds positions
+// t + T*i); kOffBand off the band.  Elements that the pruned variant never
+// touches get no offset.
+template <int L, int T, bool PR>
+__device__ __forceinline__ void band_row_offsets(unsigned (&off)[L / T], int y, int t, int h) {
+  t = opaque_lane(t);
+  const unsigned W = unsigned(2 * h + 1), row = unsigned(y) * kC;
+#pragma unroll
+  for (int i = 0; i < L / T; ++i) {
+    off[i] = kOffBand;
+    if (PR && never_in_band<L>(i)) continue;
+    const unsigned j = band_row_u(t + T * i, L, h);
+    if (j < W) off[i] = ((j >> 2) * unsigned(L * kC) + (j & 3) + row) * unsigned(sizeof(cf));
+  }
+}
+
+template <int L, int T, bool PR>
+__device__ __forceinline__ void load_band_row_buf(cf (&v)[L / T], __amdgpu_buffer_rsrc_t r,
+                                                  const unsigned (&off)[L / T]) {
+#pragma unroll
+  for (int i = 0; i < L / T; ++i) v[i] = PR && never_in_band<L>(i) ? cmake(0.f, 0.f) : buf_load(r, off[i]);
+}
+
+// Stores the band of a row (scaled); the Wp - (2h+1) pad columns are written
+// with zeros by the threads t < Wp - (2h+1).
+template <int L, int T, bool PR>
+__device__ __forceinline__ void store_band_row_buf(const cf (&v)[L / T], __amdgpu_buffer_rsrc_t r,
+                                                   const unsigned (&off)[L / T], int y, int t, int h, int Wp,
+                                                   float scale) {
+#pragma unroll
+  for (int i = 0; i < L / T; ++i)
+    if (!(PR && never_in_band<L>(i))) buf_store(r, off[i], cscale(v[i], scale));
+  for (unsigned j = unsigned(2 * h + 1 + t); j < unsigned(Wp); j += T)
+    buf_store(r, ((j >> 2) * unsigned(L * kC) + (j & 3) + unsigned(y) * kC) * unsigned(sizeof(cf)), cmake(0.f, 0.f));
+}
+
+// Band-row I/O of the k-loop row passes over a tiled array [tiles][Q][kC]
+// per kernel (kernel k at base + k * kstride).  The buffer form keeps the
+// loop-invariant byte offsets of this thread's band positions in registers
+// (pruned variants: half the positions); the plain form recomputes addresses
+// per access and is kept where the offsets would not fit: unpruned variants
+// and the long transforms of mixed radix.
+template <int Q, bool PR>
+struct BufRows {
+  static constexpr bool value = PR && (FftPlan<Q>::T <= 32 || (Q & (Q - 1)) == 0);
+};
+template <int Q, int T, bool PR, bool BUF = BufRows<Q, PR>::value>
+struct RowIO {
+  unsigned off[Q / T];
+  unsigned kbytes;
+  int y, t, h;
+  __device__ __forceinline__ RowIO(size_t kstride, int y_, int t_, int h_)
+      : kbytes(unsigned(kstride * sizeof(cf))), y(y_), t(t_), h(h_) {
+    band_row_offsets<Q, T, PR>(off, y, t, h);
+  }
+  __device__ __forceinline__ void load(cf (&v)[Q / T], const cf *base) const {
+    load_band_row_buf<Q, T, PR>(v, buf_view(base, kbytes), off);
+  }
+  __device__ __forceinline__ void store(const cf (&v)[Q / T], cf *base, int Wp, float scale) const {
+    store_band_row_buf<Q, T, PR>(v, buf_view(base, kbytes), off, y, t, h, Wp, scale);
+  }
+};
+template <int Q, int T, bool PR>
+struct RowIO<Q, T, PR, false> {
+  int y, t, h;
+  __device__ __forceinline__ RowIO(size_t, int y_, int t_, int h_) : y(y_), t(t_), h(h_) {}
+  __device__ __forceinline__ void load(cf (&v)[Q / T], const cf *base) const {
+    load_band_row<Q, T, PR>(v, base, y, t, h);
+  }
+  __device__ __forceinline__ void store(const cf (&v)[Q / T], cf *base, int Wp, float scale) const {
+    store_band_row<Q, T, PR>(v, base, y, t, h, Wp, scale);
+  }
+};
+
 // Block-wide FP64 sum in fixed order; `red` holds blockDim.x doubles.
 __device__ __forceinline__ double block_sum(double v, double *red) {
   __syncthreads();
@@ -373,11 +471,37 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_fwd(const cf *_
   }
 }
 
+// Twiddles of the k-loop passes are staged in LDS when the table is small
+// next to the exchange buffers: table reads then wait on the LDS counter only,
+// not behind the prefetched band loads in flight on the vector-memory counter
+// (which retires in order).
+template <int Q>
+struct TwLds {
+  static constexpr int entries = twiddle_table_size<Q>();
+  static constexpr bool value = entries > 0 && entries * sizeof(cf) <= 16384;
+  static constexpr size_t bytes = value ? entries * sizeof(cf) : 0;
+};
+template <int Q>
+__device__ __forceinline__ const cf *stage_twiddles(const cf *__restrict__ tw, cf *lds) {
+  if constexpr (!TwLds<Q>::value) {
+    return tw;
+  } else {
+    for (int i = threadIdx.x; i < TwLds<Q>::entries; i += blockDim.x) lds[i] = tw[i];
+    __syncthreads();
+    return lds;
+  }
+}
+
 // Occupancy target of the k-loop row passes: four wavefronts per SIMD (128
-// VGPRs) while a thread holds at most 20 values, two beyond.
+// VGPRs) while a thread holds at most 20 values, two beyond.  The pruned
+// adjoint pass of one-row-per-wavefront transforms keeps three.
 template <int Q>
 struct RowWaves {
   static constexpr int value = Q / FftPlan<Q>::T <= 20 ? 4 : 2;
+};
+template <int Q, bool PR>
+struct AdjRowWaves {
+  static constexpr int value = (PR && FftPlan<Q>::T > 32 && RowWaves<Q>::value > 3) ? 3 : RowWaves<Q>::value;
 };
 
 // ------------------------------------------------------------ forward row pass
@@ -386,29 +510,31 @@ struct RowWaves {
 // the I_Q row, keep |gx| <= 2b, scale dose/Q^2, store tiled [ntD][Q][kC] in Ib.
 template <int Q, int OUT, bool PR>
 __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf *__restrict__ Y, Epi ep, cf *__restrict__ Ib, Geo g,
-                                                    const cf *__restrict__ tw) {
+                                                    const cf *__restrict__ tw_table) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
   extern __shared__ cf smem[];
   const int row = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * RPB + row, clip = blockIdx.y;
   cf *xch = smem + row * lds_len<Q>();
+  const cf *tw = stage_twiddles<Q>(tw_table, smem + RPB * lds_len<Q>());
   float acc[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) acc[i] = 0.f;
   const size_t kstride = size_t(g.nt) * Q * kC;
   const cf *yc = Y + size_t(clip) * g.K * kstride;
+  const RowIO<Q, T, PR> io(kstride, y, t, g.b);
   // pruned variant: the band row of kernel k + 1 (half the elements) is
   // loaded while kernel k is transformed
   cf nxt[E];
-  if (PR) load_band_row<Q, T, PR>(nxt, yc, y, t, g.b);
+  if (PR) io.load(nxt, yc);
   for (int k = 0; k < g.K; ++k) {
     cf v[E];
     if (PR) {
 #pragma unroll
       for (int i = 0; i < E; ++i) v[i] = nxt[i];
-      if (k + 1 < g.K) load_band_row<Q, T, PR>(nxt, yc + (k + 1) * kstride, y, t, g.b);
+      if (k + 1 < g.K) io.load(nxt, yc + (k + 1) * kstride);
     } else {
-      load_band_row<Q, T, PR>(v, yc + k * kstride, y, t, g.b);
+      io.load(v, yc + k * kstride);
     }
     fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
@@ -439,14 +565,15 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf
 // GIN 0: G is a real [Q][Q] array per clip (Q == N), rows strided by Q.
 // GIN 1: G is a band [ntD][Q][kC] (|gx| <= 2b) per clip; its row is synthesised.
 template <int Q, int GIN, bool PR>
-__global__ __launch_bounds__(256, (PR && RowWaves<Q>::value > 3) ? 3 : RowWaves<Q>::value) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Greal,
+__global__ __launch_bounds__(256, (AdjRowWaves<Q, PR>::value)) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Greal,
                                                     size_t g_clip_stride, const cf *__restrict__ Gband, Geo g,
-                                                    const cf *__restrict__ tw) {
+                                                    const cf *__restrict__ tw_table) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
   extern __shared__ cf smem[];
   const int row = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * RPB + row, clip = blockIdx.y;
   cf *xch = smem + row * lds_len<Q>();
+  const cf *tw = stage_twiddles<Q>(tw_table, smem + RPB * lds_len<Q>());
   float gr[E];
   if constexpr (GIN == 0) {
     const float *gsrc = Greal + clip * g_clip_stride + size_t(y) * Q;
@@ -461,25 +588,26 @@ __global__ __launch_bounds__(256, (PR && RowWaves<Q>::value > 3) ? 3 : RowWaves<
   }
   const size_t kstride = size_t(g.nt) * Q * kC;
   cf *yc = Y + size_t(clip) * g.K * kstride;
+  const RowIO<Q, T, PR> io(kstride, y, t, g.b);
   // pruned variant: the band row of kernel k + 1 (half the elements) is
   // loaded while kernel k is transformed (each row is read completely before
   // this wavefront overwrites it)
   cf nxt[E];
-  if (PR) load_band_row<Q, T, PR>(nxt, yc, y, t, g.b);
+  if (PR) io.load(nxt, yc);
   for (int k = 0; k < g.K; ++k) {
     cf v[E];
     if (PR) {
 #pragma unroll
       for (int i = 0; i < E; ++i) v[i] = nxt[i];
-      if (k + 1 < g.K) load_band_row<Q, T, PR>(nxt, yc + (k + 1) * kstride, y, t, g.b);
+      if (k + 1 < g.K) io.load(nxt, yc + (k + 1) * kstride);
     } else {
-      load_band_row<Q, T, PR>(v, yc + k * kstride, y, t, g.b);
+      io.load(v, yc + k * kstride);
     }
     fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = cscale(v[i], gr[i]);
     fft<Q, -1>(v, xch, t, tw);
-    store_band_row<Q, T, PR>(v, yc + k * kstride, y, t, g.b, g.Bp, 1.0f);
+    io.store(v, yc + k * kstride, g.Bp, 1.0f);
   }
 }
 
@@ -1126,7 +1254,7 @@ int pass_x_fwd_q(const cf *Y, const EpiPtrs &ep, cf *Ib, const PassGeo &pg, cons
   Epi e = to_epi(ep);
   const bool band = g.Q != g.N;
   size_t sh = size_t(RPB) * lds_len<Q>() * sizeof(cf);
-  sh = std::max(sh, size_t(256) * sizeof(double));
+  sh = std::max(sh, size_t(256) * sizeof(double)) + dev::TwLds<Q>::bytes;
   const bool pr = dev::prunable<Q>(g.b);
   const dim3 grid(Q / RPB, nclips);
 #define LITHO_PX_FWD(OUT, PR)                                                                              \
@@ -1148,7 +1276,7 @@ int pass_x_adj_q(cf *Y, const float *G, size_t g_clip_stride, const cf *Gband, c
   constexpr int T = FftPlan<Q>::T, RPB = 256 / T;
   Geo g = to_geo(pg);
   const bool band = Gband != nullptr;
-  size_t sh = size_t(RPB) * lds_len<Q>() * sizeof(cf);
+  const size_t sh = size_t(RPB) * lds_len<Q>() * sizeof(cf) + dev::TwLds<Q>::bytes;
   const bool pr = dev::prunable<Q>(g.b);
   const dim3 grid(Q / RPB, nclips);
 #define LITHO_PX_ADJ(GIN, PR)                                                                              \
