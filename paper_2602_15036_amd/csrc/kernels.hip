@@ -423,6 +423,27 @@ __global__ __launch_bounds__(ColBlock<L>::threads) void k_col_fft(const cf *__re
   }
 }
 
+// Twiddles of the k-loop passes are staged in LDS when the table is small
+// next to the exchange buffers: table reads then wait on the LDS counter only,
+// not behind the prefetched band loads in flight on the vector-memory counter
+// (which retires in order).
+template <int Q>
+struct TwLds {
+  static constexpr int entries = twiddle_table_size<Q>();
+  static constexpr bool value = entries > 0 && entries * sizeof(cf) <= 16384;
+  static constexpr size_t bytes = value ? entries * sizeof(cf) : 0;
+};
+template <int Q>
+__device__ __forceinline__ const cf *stage_twiddles(const cf *__restrict__ tw, cf *lds) {
+  if constexpr (!TwLds<Q>::value) {
+    return tw;
+  } else {
+    for (int i = threadIdx.x; i < TwLds<Q>::entries; i += blockDim.x) lds[i] = tw[i];
+    __syncthreads();
+    return lds;
+  }
+}
+
 // ------------------------------------------------------------ forward column pass
 // Y_k[jt][y][c] = sum_ky Phi'_k(ky, j) Mh(ky, j) exp(+2 pi i ky y / Q), for the
 // kernels k0 .. k0 + kpb - 1 of this block: the mask-spectrum column stays in
@@ -430,7 +451,7 @@ __global__ __launch_bounds__(ColBlock<L>::threads) void k_col_fft(const cf *__re
 template <int Q, bool PR>
 __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_fwd(const cf *__restrict__ bank,
                                                                     const cf *__restrict__ Mh, cf *__restrict__ Y,
-                                                                    Geo g, const cf *__restrict__ tw, int kpb) {
+                                                                    Geo g, const cf *__restrict__ tw_table, int kpb) {
   constexpr int T = FftPlan<Q>::T, E = Q / T;
   extern __shared__ cf smem[];
   int jt, c, t;
@@ -438,6 +459,7 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_fwd(const cf *_
   col_coords<Q>(g.nt, jt, c, t, valid);
   const int k0 = blockIdx.y * kpb, k1 = min(g.K, k0 + kpb), clip = blockIdx.z;
   cf *buf = smem + (threadIdx.x / T) * lds_len<Q>();
+  const cf *tw = stage_twiddles<Q>(tw_table, smem + (ColBlock<Q>::threads / T) * lds_len<Q>());
   const size_t kb = size_t(g.nt) * g.B * kC;
   const cf *ph = bank + (size_t(g.p) * g.Kbank * g.nt + jt) * g.B * kC + c;
   const cf *mh = Mh + (size_t(clip) * g.nt + jt) * g.B * kC + c;
@@ -468,27 +490,6 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_fwd(const cf *_
 #pragma unroll
       for (int i = 0; i < E; ++i) dst[(tt + T * i) * kC] = v[i];
     }
-  }
-}
-
-// Twiddles of the k-loop passes are staged in LDS when the table is small
-// next to the exchange buffers: table reads then wait on the LDS counter only,
-// not behind the prefetched band loads in flight on the vector-memory counter
-// (which retires in order).
-template <int Q>
-struct TwLds {
-  static constexpr int entries = twiddle_table_size<Q>();
-  static constexpr bool value = entries > 0 && entries * sizeof(cf) <= 16384;
-  static constexpr size_t bytes = value ? entries * sizeof(cf) : 0;
-};
-template <int Q>
-__device__ __forceinline__ const cf *stage_twiddles(const cf *__restrict__ tw, cf *lds) {
-  if constexpr (!TwLds<Q>::value) {
-    return tw;
-  } else {
-    for (int i = threadIdx.x; i < TwLds<Q>::entries; i += blockDim.x) lds[i] = tw[i];
-    __syncthreads();
-    return lds;
   }
 }
 
@@ -619,7 +620,7 @@ template <int Q, bool PR>
 __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *__restrict__ V,
                                                                     const cf *__restrict__ bank,
                                                                     double2 *__restrict__ part, Geo g,
-                                                                    const cf *__restrict__ tw) {
+                                                                    const cf *__restrict__ tw_table) {
   constexpr int T = FftPlan<Q>::T, E = Q / T;
   extern __shared__ cf smem[];
   int jt, c, t;
@@ -627,6 +628,7 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *_
   col_coords<Q>(g.nt, jt, c, t, valid);
   const int kc = blockIdx.y, clip = blockIdx.z;
   cf *buf = smem + (threadIdx.x / T) * lds_len<Q>();
+  const cf *tw = stage_twiddles<Q>(tw_table, smem + (ColBlock<Q>::threads / T) * lds_len<Q>());
   cf acc[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) acc[i] = cmake(0.f, 0.f);
@@ -1228,7 +1230,7 @@ template <int Q>
 int pass_y_fwd_q(const cf *bank, const cf *Mh, cf *Y, const PassGeo &pg, const cf *twQ, int nclips,
                  hipStream_t s) {
   Geo g = to_geo(pg);
-  constexpr size_t sh = col_lds<Q>();
+  constexpr size_t sh = col_lds<Q>() + dev::TwLds<Q>::bytes;
   // kernels per block: enough blocks to fill the device (~2560), the rest
   // looped inside a block
   const int per_k = col_blocks<Q>(g.nt) * nclips;
@@ -1297,7 +1299,7 @@ template <int Q>
 int pass_y_adj_q(const cf *V, const cf *bank, double2 *part, const PassGeo &pg, const cf *twQ, int nclips,
                  hipStream_t s) {
   Geo g = to_geo(pg);
-  constexpr size_t sh = col_lds<Q>();
+  constexpr size_t sh = col_lds<Q>() + dev::TwLds<Q>::bytes;
   const dim3 grid(col_blocks<Q>(g.nt), g.KC, nclips);
   if (dev::prunable<Q>(g.b))
     return launch("pass_y_adj", KPTR(dev::k_pass_y_adj<Q, true>), grid, sh, s, [&] {
