@@ -205,6 +205,23 @@ __device__ __forceinline__ void store_band_row_buf(const cf (&v)[L / T], __amdgp
     buf_store(r, ((j >> 2) * unsigned(L * kC) + (j & 3) + unsigned(y) * kC) * unsigned(sizeof(cf)), cmake(0.f, 0.f));
 }
 
+// One band row of a tiled array [tiles][L][kC] of `bytes` bytes at a uniform
+// base, through buffer loads/stores (offsets formed here, once per row).
+template <int L, int T, bool PR = false>
+__device__ __forceinline__ void load_band_row_v(cf (&v)[L / T], const cf *base, unsigned bytes, int y, int t,
+                                                int h) {
+  unsigned off[L / T];
+  band_row_offsets<L, T, PR>(off, y, t, h);
+  load_band_row_buf<L, T, PR>(v, buf_view(base, bytes), off);
+}
+template <int L, int T, bool PR = false>
+__device__ __forceinline__ void store_band_row_v(const cf (&v)[L / T], cf *base, unsigned bytes, int y, int t,
+                                                 int h, int Wp, float scale) {
+  unsigned off[L / T];
+  band_row_offsets<L, T, PR>(off, y, t, h);
+  store_band_row_buf<L, T, PR>(v, buf_view(base, bytes), off, y, t, h, Wp, scale);
+}
+
 // Band-row I/O of the k-loop row passes over a tiled array [tiles][Q][kC]
 // per kernel (kernel k at base + k * kstride).  The buffer form keeps the
 // loop-invariant byte offsets of this thread's band positions in registers
@@ -255,17 +272,42 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return red[0];
 }
 
-// Image epilogue at pixel (y, x) of the N grid: image write, sigmoid resist,
-// residual G = 2 w (Z - T) a Z (1 - Z); returns w (Z - T)^2 (0 without
-// target), w the plane's loss weight.
-__device__ __forceinline__ double image_epilogue(const Epi &ep, const Geo &g, int clip, int y, int x, float I) {
-  const size_t NN = size_t(g.N) * g.N;
-  if (ep.image) ep.image[(size_t(clip) * g.P + g.p) * NN + size_t(y) * g.N + x] = I;
+// Image epilogue over row y of the N grid, held in the FFT register layout
+// (thread t holds x = t + T*i): image write, sigmoid resist Z, residual
+// G = 2 w (Z - T) a Z (1 - Z); returns the row's w (Z - T)^2 (0 without
+// target), w the plane's loss weight.  Row pointers are formed once, so every
+// access is the row base plus an immediate offset; the target row is read
+// beforehand (load_target_row) so that its latency overlaps the transform.
+template <int E, int T>
+__device__ __forceinline__ void load_target_row(const Epi &ep, const Geo &g, int clip, int y, int t,
+                                                float (&tg)[E]) {
+#pragma unroll
+  for (int i = 0; i < E; ++i) tg[i] = 0.f;
+  if (!ep.target) return;
+  const float *src = ep.target + (size_t(clip) * g.N + y) * g.N + t;
+#pragma unroll
+  for (int i = 0; i < E; ++i) tg[i] = src[T * i];
+}
+template <int E, int T>
+__device__ __forceinline__ double image_epilogue_row(const Epi &ep, const Geo &g, int clip, int y, int t,
+                                                     const float (&I)[E], const float (&tg)[E]) {
+  const size_t NN = size_t(g.N) * g.N, ro = size_t(y) * g.N + t;
+  if (ep.image) {
+    float *img = ep.image + (size_t(clip) * g.P + g.p) * NN + ro;
+#pragma unroll
+    for (int i = 0; i < E; ++i) img[T * i] = I[i];
+  }
   if (!ep.target) return 0.0;
-  const float z = 1.0f / (1.0f + expf(-g.slope * (I - g.thr)));
-  const float d = z - ep.target[size_t(clip) * NN + size_t(y) * g.N + x];
-  ep.G[size_t(clip) * NN + size_t(y) * g.N + x] = 2.0f * g.pw * d * g.slope * z * (1.0f - z);
-  return double(g.pw) * double(d) * double(d);
+  float *G = ep.G + size_t(clip) * NN + ro;
+  double l = 0.0;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const float z = 1.0f / (1.0f + expf(-g.slope * (I[i] - g.thr)));
+    const float d = z - tg[i];
+    G[T * i] = 2.0f * g.pw * d * g.slope * z * (1.0f - z);
+    l += double(g.pw) * double(d) * double(d);
+  }
+  return l;
 }
 
 // ------------------------------------------------------------ real rows -> band
@@ -278,7 +320,7 @@ __device__ __forceinline__ double image_epilogue(const Epi &ep, const Geo &g, in
 // Two real rows share one complex transform: Z = DFT(r0 + i r1) gives
 // DFT(r0)[k] = (Z[k] + conj Z[-k]) / 2 and DFT(r1)[k] = (Z[k] - conj Z[-k]) / 2i,
 // with Z[-k] read back through the transform's LDS region.
-template <int L>
+template <int L, bool PR>
 __global__ __launch_bounds__(256) void k_rows_fwd_real(const float *__restrict__ in, size_t in_clip,
                                                        cf *__restrict__ out, int h, int Wp,
                                                        const cf *__restrict__ tw, float scale) {
@@ -309,8 +351,9 @@ __global__ __launch_bounds__(256) void k_rows_fwd_real(const float *__restrict__
   }
   if (!store) return;
   cf *dst = out + size_t(clip) * (Wp / kC) * L * kC;
-  store_band_row<L, T>(v, dst, y0, t, h, Wp, scale);
-  store_band_row<L, T>(w, dst, y0 + 1, t, h, Wp, scale);
+  const unsigned bytes = unsigned(size_t(Wp) * L * sizeof(cf));
+  store_band_row_v<L, T, PR>(v, dst, bytes, y0, t, h, Wp, scale);
+  store_band_row_v<L, T, PR>(w, dst, bytes, y0 + 1, t, h, Wp, scale);
 }
 
 // ------------------------------------------------------------ band rows -> real rows
@@ -319,7 +362,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd_real(const float *__restrict__
 // image rows are real, so their band rows are Hermitian and MODE 1 sends two
 // rows through one complex transform: X_y0 + i X_y1 yields row y0 in the real
 // part and row y1 in the imaginary part (rows 2 (block RPB + row) and + 1).
-template <int L, int MODE>
+template <int L, int MODE, bool PR>
 __global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in, int h, int Wp,
                                                        float *__restrict__ out, Epi ep, Geo g,
                                                        const cf *__restrict__ tw, float scale) {
@@ -331,7 +374,7 @@ __global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in
   cf v[E];
   if constexpr (MODE == 0) {
     const int y = blockIdx.x * RPB + row;
-    load_band_row<L, T>(v, src, y, t, h);
+    load_band_row_v<L, T, PR>(v, src, unsigned(size_t(Wp) * L * sizeof(cf)), y, t, h);
     fft<L, +1>(v, smem + row * lds_len<L>(), t, tw);
     float *dst = out + (size_t(clip) * L + y) * L;
 #pragma unroll
@@ -342,18 +385,25 @@ __global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in
     const bool store = yp < L;
     const int y0 = store ? yp : L - 2;
     cf b[E];
-    load_band_row<L, T>(v, src, y0, t, h);
-    load_band_row<L, T>(b, src, y0 + 1, t, h);
+    const unsigned bytes = unsigned(size_t(Wp) * L * sizeof(cf));
+    load_band_row_v<L, T, PR>(v, src, bytes, y0, t, h);
+    load_band_row_v<L, T, PR>(b, src, bytes, y0 + 1, t, h);
+    float tg0[E], tg1[E];
+    load_target_row<E, T>(ep, g, clip, y0, t, tg0);
+    load_target_row<E, T>(ep, g, clip, y0 + 1, t, tg1);
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = cmake(v[i].x - b[i].y, v[i].y + b[i].x);
     fft<L, +1>(v, smem + row * lds_len<L>(), t, tw);
     double lsum = 0.0;
     if (store) {
+      float I0[E], I1[E];
 #pragma unroll
       for (int i = 0; i < E; ++i) {
-        lsum += image_epilogue(ep, g, clip, y0, t + T * i, scale * v[i].x);
-        lsum += image_epilogue(ep, g, clip, y0 + 1, t + T * i, scale * v[i].y);
+        I0[i] = scale * v[i].x;
+        I1[i] = scale * v[i].y;
       }
+      lsum = image_epilogue_row<E, T>(ep, g, clip, y0, t, I0, tg0) +
+             image_epilogue_row<E, T>(ep, g, clip, y0 + 1, t, I1, tg1);
     }
     if (ep.target) {
       const double s = block_sum(lsum, reinterpret_cast<double *>(smem));
@@ -542,9 +592,11 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf
     for (int i = 0; i < E; ++i) acc[i] += cabs2(v[i]);
   }
   if constexpr (OUT == 0) {
-    double lsum = 0.0;
+    float tg[E], I[E];
+    load_target_row<E, T>(ep, g, clip, y, t, tg);
 #pragma unroll
-    for (int i = 0; i < E; ++i) lsum += image_epilogue(ep, g, clip, y, t + T * i, acc[i] * g.dose);
+    for (int i = 0; i < E; ++i) I[i] = acc[i] * g.dose;
+    const double lsum = image_epilogue_row<E, T>(ep, g, clip, y, t, I, tg);
     if (ep.target) {
       const double s = block_sum(lsum, reinterpret_cast<double *>(smem));
       if (threadIdx.x == 0) ep.loss_part[(size_t(clip) * g.P + g.p) * gridDim.x + blockIdx.x] = s;
@@ -554,8 +606,8 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = cmake(acc[i], 0.f);
     fft<Q, -1>(v, xch, t, tw);
-    store_band_row<Q, T>(v, Ib + size_t(clip) * g.ntD * size_t(Q) * kC, y, t, 2 * g.b, g.Dp,
-                         g.dose / (float(Q) * float(Q)));
+    store_band_row_v<Q, T>(v, Ib + size_t(clip) * g.ntD * size_t(Q) * kC, unsigned(size_t(g.Dp) * Q * sizeof(cf)),
+                           y, t, 2 * g.b, g.Dp, g.dose / (float(Q) * float(Q)));
   }
 }
 
@@ -582,7 +634,8 @@ __global__ __launch_bounds__(256, (AdjRowWaves<Q, PR>::value)) void k_pass_x_adj
     for (int i = 0; i < E; ++i) gr[i] = gsrc[t + T * i] * g.dose;
   } else {
     cf v[E];
-    load_band_row<Q, T>(v, Gband + size_t(clip) * g.ntD * size_t(Q) * kC, y, t, 2 * g.b);
+    load_band_row_v<Q, T>(v, Gband + size_t(clip) * g.ntD * size_t(Q) * kC, unsigned(size_t(g.Dp) * Q * sizeof(cf)),
+                          y, t, 2 * g.b);
     fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) gr[i] = v[i].x * g.dose;
@@ -1186,8 +1239,12 @@ int rows_fwd_real_l(const char *name, const float *in, size_t in_clip, cf *out, 
   constexpr int T = FftPlan<L>::T, RPB = 256 / T;
   size_t sh = size_t(RPB) * lds_len<L>() * sizeof(cf);
   const dim3 grid((L / RPB + 1) / 2, nclips);  // two rows per transform
-  return launch(name, KPTR(dev::k_rows_fwd_real<L>), grid, sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_rows_fwd_real<L>, grid, dim3(256), sh, s, in, in_clip, out, h, Wp, tw, scale);
+  if (dev::prunable<L>(h))
+    return launch(name, KPTR(dev::k_rows_fwd_real<L, true>), grid, sh, s, [&] {
+      hipLaunchKernelGGL((dev::k_rows_fwd_real<L, true>), grid, dim3(256), sh, s, in, in_clip, out, h, Wp, tw, scale);
+    });
+  return launch(name, KPTR(dev::k_rows_fwd_real<L, false>), grid, sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_rows_fwd_real<L, false>), grid, dim3(256), sh, s, in, in_clip, out, h, Wp, tw, scale);
   });
 }
 
@@ -1200,8 +1257,14 @@ int rows_inv_real_l(const char *name, const cf *in, int h, int Wp, float *out, c
   Geo g = to_geo(pg);
   Epi e = to_epi(ep);
   const dim3 grid(MODE == 1 ? (L / RPB + 1) / 2 : L / RPB, nclips);  // MODE 1: two rows per transform
-  return launch(name, KPTR(dev::k_rows_inv_real<L, MODE>), grid, sh, s, [&] {
-    hipLaunchKernelGGL((dev::k_rows_inv_real<L, MODE>), grid, dim3(256), sh, s, in, h, Wp, out, e, g, tw, scale);
+  if (dev::prunable<L>(h))
+    return launch(name, KPTR((dev::k_rows_inv_real<L, MODE, true>)), grid, sh, s, [&] {
+      hipLaunchKernelGGL((dev::k_rows_inv_real<L, MODE, true>), grid, dim3(256), sh, s, in, h, Wp, out, e, g, tw,
+                         scale);
+    });
+  return launch(name, KPTR((dev::k_rows_inv_real<L, MODE, false>)), grid, sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_rows_inv_real<L, MODE, false>), grid, dim3(256), sh, s, in, h, Wp, out, e, g, tw,
+                       scale);
   });
 }
 
