@@ -168,6 +168,11 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, f), r, int(off), 0, 0);
 }
 
+using d2v = double __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ d2v buf_load_d2(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, int(off), 0, 0));
+}
+
 // Byte offsets of the band row |f| <= h of row y of a tiled array
 // [tiles][L][kC] in the FFT register layout (thread t holds positions
 // t + T*i); kOffBand off the band.  Elements that the pruned variant never
@@ -454,14 +459,17 @@ __global__ __launch_bounds__(ColBlock<L>::threads) void k_col_fft(const cf *__re
   cf *buf = smem + (threadIdx.x / T) * lds_len<L>();
   const int rin = in_h < 0 ? L : 2 * in_h + 1;
   const int rout = out_h < 0 ? L : 2 * out_h + 1;
-  const cf *src = in + clip * in_clip + size_t(jt) * rin * kC + c;
-  cf *dst = out + clip * out_clip + size_t(jt) * rout * kC + c;
+  // buffer views of this clip's arrays; positions off the band read as zero
+  // and are not written (buffer range checking)
+  const auto src = buf_view(in + clip * in_clip, unsigned(size_t(nt) * rin * kC * sizeof(cf)));
+  const auto dst = buf_view(out + clip * out_clip, unsigned(size_t(nt) * rout * kC * sizeof(cf)));
+  const unsigned in0 = unsigned(jt * rin * kC + c), out0 = unsigned(jt * rout * kC + c);
   cf v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int pos = t + T * i;
     const int r = in_h < 0 ? pos : band_row_of(pos, L, in_h);
-    v[i] = r >= 0 ? src[r * kC] : cmake(0.f, 0.f);
+    v[i] = buf_load(src, r >= 0 ? (in0 + unsigned(r) * kC) * unsigned(sizeof(cf)) : kOffBand);
   }
   fft<L, DIR>(v, buf, t, tw);
   if (!valid) return;
@@ -469,7 +477,7 @@ __global__ __launch_bounds__(ColBlock<L>::threads) void k_col_fft(const cf *__re
   for (int i = 0; i < E; ++i) {
     const int pos = t + T * i;
     const int r = out_h < 0 ? pos : band_row_of(pos, L, out_h);
-    if (r >= 0) dst[r * kC] = cscale(v[i], scale);
+    buf_store(dst, r >= 0 ? (out0 + unsigned(r) * kC) * unsigned(sizeof(cf)) : kOffBand, cscale(v[i], scale));
   }
 }
 
@@ -742,7 +750,7 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *_
 // ------------------------------------------------------------ gradient finish, columns
 // Acc = sum over (plane, k-chunk) partials in FP64 (fixed order), scaled by 1/N^2,
 // then the inverse column DFT (band rows -> N rows).
-template <int N>
+template <int N, bool PR>
 __global__ __launch_bounds__(ColBlock<N>::threads) void k_grad_cols(const double2 *__restrict__ part, int nparts,
                                                                    cf *__restrict__ out, Geo g,
                                                                    const cf *__restrict__ tw) {
@@ -754,21 +762,33 @@ __global__ __launch_bounds__(ColBlock<N>::threads) void k_grad_cols(const double
   const int clip = blockIdx.y;
   cf *buf = smem + (threadIdx.x / T) * lds_len<N>();
   const size_t nE = size_t(g.B) * kC;
-  const double2 *src = part + (size_t(clip) * nparts * g.nt + jt) * nE + c;
+  const double2 *src = part + size_t(clip) * nparts * g.nt * nE;
+  const unsigned pbytes = unsigned(g.nt * nE * sizeof(double2));
   const double inv = 1.0 / (double(N) * double(N));
-  cf v[E];
+  // byte offsets of this thread's band rows in one partial (off the band:
+  // out of range, read as zero)
+  unsigned off[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int r = band_row_of(t + T * i, N, g.b);
-    double sx = 0.0, sy = 0.0;
-    if (r >= 0)
-      for (int s = 0; s < nparts; ++s) {
-        const double2 a = src[size_t(s) * g.nt * nE + r * kC];
-        sx += a.x;
-        sy += a.y;
-      }
-    v[i] = cmake(float(sx * inv), float(sy * inv));
+    off[i] = r >= 0 ? unsigned(jt * nE + r * kC + c) * unsigned(sizeof(double2)) : kOffBand;
   }
+  double sx[E], sy[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) sx[i] = sy[i] = 0.0;
+  for (int s = 0; s < nparts; ++s) {
+    const auto view = buf_view(src + size_t(s) * g.nt * nE, pbytes);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      if (PR && never_in_band<N>(i)) continue;
+      const d2v a = buf_load_d2(view, off[i]);
+      sx[i] += a.x;
+      sy[i] += a.y;
+    }
+  }
+  cf v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] = cmake(float(sx[i] * inv), float(sy[i] * inv));
   fft<N, +1>(v, buf, t, tw);
   if (!valid) return;
   cf *dst = out + (size_t(clip) * g.nt + jt) * size_t(N) * kC + c;
@@ -1381,9 +1401,14 @@ int grad_cols_n(const double2 *part, int nparts, cf *tmp, const PassGeo &pg, con
   Geo g = to_geo(pg);
   constexpr size_t sh = col_lds<N>();
   const dim3 grid(col_blocks<N>(g.nt), nclips);
-  return launch("grad_cols", KPTR(dev::k_grad_cols<N>), grid, sh, s, [&] {
-    hipLaunchKernelGGL(dev::k_grad_cols<N>, grid, dim3(dev::ColBlock<N>::threads), sh, s, part, nparts, tmp, g,
-                       twN);
+  if (dev::prunable<N>(g.b))
+    return launch("grad_cols", KPTR(dev::k_grad_cols<N, true>), grid, sh, s, [&] {
+      hipLaunchKernelGGL((dev::k_grad_cols<N, true>), grid, dim3(dev::ColBlock<N>::threads), sh, s, part, nparts,
+                         tmp, g, twN);
+    });
+  return launch("grad_cols", KPTR(dev::k_grad_cols<N, false>), grid, sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_grad_cols<N, false>), grid, dim3(dev::ColBlock<N>::threads), sh, s, part, nparts,
+                       tmp, g, twN);
   });
 }
 
