@@ -562,13 +562,25 @@ template <int Q, bool PR>
 struct AdjRowWaves {
   static constexpr int value = (PR && FftPlan<Q>::T > 32 && RowWaves<Q>::value > 3) ? 3 : RowWaves<Q>::value;
 };
+// Waves per SIMD that the LDS of a 256-thread row-pass block (exchange rows
+// and staged twiddles) allows on a 160 KB CU; a register target above it buys
+// nothing and only constrains the schedule.
+template <int Q>
+struct RowLdsWaves {
+  static constexpr size_t bytes = size_t(256 / FftPlan<Q>::T) * lds_len<Q>() * sizeof(cf) + TwLds<Q>::bytes;
+  static constexpr int value = int(163840 / bytes) < 1 ? 1 : int(163840 / bytes);
+};
+template <int W, int Q>
+struct CapWaves {
+  static constexpr int value = W < RowLdsWaves<Q>::value ? W : RowLdsWaves<Q>::value;
+};
 
 // ------------------------------------------------------------ forward row pass
 // I_Q(y, x) = dose * sum_k |sum_kx Y_k(y, kx) exp(+2 pi i kx x / Q)|^2.
 // OUT 0 (Q == N): image / resist epilogue.  OUT 1 (Q < N): forward row DFT of
 // the I_Q row, keep |gx| <= 2b, scale dose/Q^2, store tiled [ntD][Q][kC] in Ib.
 template <int Q, int OUT, bool PR>
-__global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf *__restrict__ Y, Epi ep, cf *__restrict__ Ib, Geo g,
+__global__ __launch_bounds__(256, (CapWaves<RowWaves<Q>::value, Q>::value)) void k_pass_x_fwd(const cf *__restrict__ Y, Epi ep, cf *__restrict__ Ib, Geo g,
                                                     const cf *__restrict__ tw_table) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
   extern __shared__ cf smem[];
@@ -626,7 +638,7 @@ __global__ __launch_bounds__(256, RowWaves<Q>::value) void k_pass_x_fwd(const cf
 // GIN 0: G is a real [Q][Q] array per clip (Q == N), rows strided by Q.
 // GIN 1: G is a band [ntD][Q][kC] (|gx| <= 2b) per clip; its row is synthesised.
 template <int Q, int GIN, bool PR>
-__global__ __launch_bounds__(256, (AdjRowWaves<Q, PR>::value)) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Greal,
+__global__ __launch_bounds__(256, (CapWaves<AdjRowWaves<Q, PR>::value, Q>::value)) void k_pass_x_adj(cf *__restrict__ Y, const float *__restrict__ Greal,
                                                     size_t g_clip_stride, const cf *__restrict__ Gband, Geo g,
                                                     const cf *__restrict__ tw_table) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
