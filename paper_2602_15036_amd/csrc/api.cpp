@@ -383,12 +383,14 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
   g.ntD = g.Dp / kTileCols;
   g.K = K_use; g.Kbank = h.K; g.P = h.n_focus; g.dose = h.dose;
   // k-chunks of the adjoint column pass: enough blocks to fill the device
-  // (~4096), each chunk summing kper kernels in FP32 before the FP64 reduction.
-  // The GEMM form has one workgroup per 32-column block of the band (~1024).
+  // (~2048: eight per CU; more chunks only add FP64 partials for the gradient
+  // columns to read), each chunk summing kper kernels in FP32 before the FP64
+  // reduction.  The GEMM form has one workgroup per 32-column block of the
+  // band (~1024).
   {
     const bool gemm = prec != LITHO_PREC_FP32;
     const size_t units = gemm ? size_t(adj_gemm_blocks(g.Bp, g.B)) * batch : size_t(g.nt) * batch;
-    const size_t target = gemm ? 1024 : 4096;
+    const size_t target = gemm ? 1024 : 2048;
     const int want = int((target + units - 1) / units);
     const int kc = std::max(1, std::min(K_use, want));
     g.kper = (K_use + kc - 1) / kc;
