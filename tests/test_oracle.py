@@ -4,6 +4,8 @@ The paper prints no image values, so every pin here is a brute-force
 equality, a closed form, an invariant or an adjoint identity.
 """
 import math
+import os
+import sys
 
 import numpy as np
 import pytest
@@ -374,3 +376,32 @@ def test_plane_weighted_gradient_matches_central_finite_differences():
     fd = O.fd_gradient(m, T, banks, 50.0, 0.3, pix, h=1e-5, weights=wts)
     got = np.array([g[p] for p in pix])
     assert np.abs(got - fd).max() < 1e-7 * np.abs(fd).max()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_gradient_matches_stored_fd_at_every_pixel_64():
+    # the adjoint formula against FP64 central differences of the loss at all
+    # 4096 pixels of the 64 x 64 three-plane clip (tests/golden/make_fd64_every_pixel.py)
+    sys.path.insert(0, GOLDEN)
+    import make_fd64_every_pixel as M
+    gold = np.load(os.path.join(GOLDEN, "fd64_every_pixel.npz"))
+    spec, m, T = M.inputs()
+    banks = [O.socs_kernels(spec, F, K=spec.K) for F in spec.focus_nm]
+    Lo, g, _ = O.gradient(m, T, banks, 50.0, 0.3)
+    fd = gold["fd"]
+    assert abs(Lo - float(gold["loss"])) < 1e-12 * Lo
+    assert np.linalg.norm(g - fd) / np.linalg.norm(fd) < 1e-7
+    assert np.abs(g - fd).max() < 1e-7 * np.abs(fd).max()
+
+
+def test_stored_directional_fd_2048_is_consistent():
+    # the stored 2048 x 2048 directional differences: second-order agreement of
+    # the two step sizes, and the oracle's analytic <grad, v> within 1e-7
+    gold = np.load(os.path.join(GOLDEN, "fd2048_directions.npz"))
+    fd, rich, an = gold["fd"], gold["fd_richardson"], gold["analytic"]
+    assert fd.shape == (2, 8) and gold["v"].shape == (8, 64, 64)
+    assert np.allclose(np.linalg.norm(gold["v"].reshape(8, -1), axis=1), 1.0)
+    assert np.all(np.abs(fd[0] - fd[1]) < 1e-5 * np.abs(fd[0]))
+    assert np.all(np.abs(rich - an) < 1e-7 * np.abs(an))
