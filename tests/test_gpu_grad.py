@@ -174,23 +174,6 @@ def test_vjp_mode_resampled_grid(L):
     assert rel_l2(grad.cpu().numpy()[0], go) < GTOL
 
 
-def test_through_focus_gradient_2048():
-    # 2048 x 2048, three focus planes, K = 24: full gradient and a 64 x 64 crop
-    from paper_2602_15036_amd import litho as L
-    spec = W.CONFIG3
-    bank = L.Bank.from_spec(spec)
-    assert bank.inner_grid == 1280
-    m = W.as_f32_exact(W.curvilinear_mask(2048, 2000))
-    T = W.manhattan_target(2048, 2001)
-    _, loss, grad = L.image_grad(bank, dev(m[None]), target=dev(T[None]), slope=SLOPE, threshold=THR,
-                                 want_image=False)
-    Lo, go, _ = O.gradient(m, T, _banks(spec, 24), SLOPE, THR, method="fft")
-    g = grad.cpu().numpy()[0]
-    assert abs(loss.item() - Lo) < 1e-5 * Lo
-    assert rel_l2(g, go) < GTOL
-    assert rel_l2(g[992:1056, 992:1056], go[992:1056, 992:1056]) < GTOL
-
-
 def test_plane_weighted_loss_and_gradient(L):
     # through-focus loss with unequal plane weights against the oracle
     spec = W.fd_clip_optics(128).with_(K=10)

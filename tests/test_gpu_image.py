@@ -95,45 +95,6 @@ def test_clear_and_dark_field(L):
     assert np.abs(img[1, 0]).max() == 0.0
 
 
-@pytest.mark.parametrize("inner", [0, 768, 1024])
-def test_bench_launch_config_sampled_pixels(L, inner):
-    # 1024 x 1024, K = 24, batch of 16 curvilinear clips: the bench workload
-    spec = W.CONFIG2
-    bank = L.Bank.from_spec(spec)
-    bank.set_inner_grid(inner)
-    assert bank.inner_grid == (640 if inner == 0 else inner)
-    masks = np.stack([W.as_f32_exact(W.curvilinear_mask(1024, 1000 + s)) for s in range(16)])
-    img = L.image(bank, dev(masks)).cpu().numpy()
-    assert np.isfinite(img).all() and img.min() >= 0
-    lam, phi = O.socs_kernels(spec, 0.0, K=24)
-    b = bank.b
-    rng = np.random.default_rng(7)
-    for i in (0, 7, 15):
-        mh = O.mask_spectrum(masks[i], b, "fft")
-        ys = rng.integers(0, 1024, 40)
-        xs = rng.integers(0, 1024, 40)
-        ref = O.image_at(mh, lam, phi, 1024, ys, xs)
-        got = img[i, 0][ys, xs]
-        assert rel_l2(got, ref) < TOL, i
-
-
-def test_large_grid_sampled_pixels(L):
-    # 2048 x 2048 through focus (3 planes, K = 24): sampled pixels per plane
-    spec = W.CONFIG3
-    bank = L.Bank.from_spec(spec)
-    m = W.as_f32_exact(W.curvilinear_mask(2048, 2000))
-    img = L.image(bank, dev(m[None])).cpu().numpy()[0]
-    b = bank.b
-    mh = O.mask_spectrum(m, b, "fft")
-    rng = np.random.default_rng(11)
-    ys = rng.integers(0, 2048, 24)
-    xs = rng.integers(0, 2048, 24)
-    for p, F in enumerate(spec.focus_nm):
-        lam, phi = O.socs_kernels(spec, F, K=24)
-        ref = O.image_at(mh, lam, phi, 2048, ys, xs)
-        assert rel_l2(img[p][ys, xs], ref) < TOL, p
-
-
 def test_inner_grid_validation(L):
     bank = L.Bank.from_spec(W.CONFIG2.with_(n=256, K=4))
     assert bank.inner_grid == 160
