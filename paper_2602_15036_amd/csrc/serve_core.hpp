@@ -200,7 +200,10 @@ class Scheduler {
       if (!any_running && queue_.empty())
         cv_work_.wait(lk, [&] { return stop_ || !queue_.empty(); });
       else
-        timed_wait(cv_work_, lk, poll_us_, [&] { return stop_; });
+        // requests are running (or queued behind a full device): check again
+        // after the poll interval; a stop does not cut the wait short, so
+        // draining does not spin
+        timed_wait(cv_work_, lk, poll_us_, [] { return false; });
     }
   }
 
