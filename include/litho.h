@@ -178,17 +178,31 @@ void litho_kernels_free(litho_bank_t *bank);
 int litho_image(const litho_bank_t *bank, const float *d_mask, int batch, int K_use,
                 float *d_image, int prec, void *hip_stream);
 
+/* Loss of the fused mode: the squared or the absolute resist mismatch. */
+enum { LITHO_LOSS_L2 = 0, LITHO_LOSS_L1 = 1 };
+
 typedef struct litho_resist {
   double slope;       /* a of the sigmoid resist (e.g. 50) */
   double threshold;   /* t, relative to the open-frame intensity (e.g. 0.3) */
   const double *plane_weight;  /* h_[n_focus] weights w_p of the planes' losses, or NULL (all 1) */
+  /* Resist kernel K_resist of Eq. 5: a Gaussian of this standard deviation in
+   * pixels (0 = delta, no blur).  The resist then sees R = I (x) K_resist
+   * (periodic convolution; exact through the band |f| <= 2b that carries I)
+   * and the residual is blurred back, dL/dI = K_resist (x) dL/dR. */
+  double blur_sigma_px;
+  /* LITHO_LOSS_L2: L = sum w_p (Z - T)^2.  LITHO_LOSS_L1: L = sum w_p |Z - T|,
+   * the sigmoid relaxation of the lithography-consistency loss of Eqs. 15 and
+   * 17 (T = Z_round of Eq. 16, t = tau_print), dL/dZ = w_p sign(Z - T). */
+  int loss;
 } litho_resist_t;
 
 /* Forward image plus the ILT adjoint (mask gradient).
  * Two modes:
- *   fused loss  (d_target != NULL): Z = sigmoid(a (I - t)),
- *                L = sum_planes w_p sum_r (Z - T)^2 per clip,
- *                G = dL/dI = 2 w_p (Z - T) a Z (1 - Z); resist must be non-NULL.
+ *   fused loss  (d_target != NULL): Z = sigmoid(a (R - t)) with R = I, or
+ *                R = I (x) K_resist when resist->blur_sigma_px > 0,
+ *                L = sum_planes w_p sum_r (Z - T)^2 per clip (|Z - T| for LITHO_LOSS_L1),
+ *                G = dL/dI = K_resist (x) [2 w_p (Z - T) a Z (1 - Z)] (L1: w_p sign(Z - T) a Z (1 - Z));
+ *                resist must be non-NULL.  With blur, d_image receives R.
  *   VJP         (d_target == NULL): G = d_grad_image, [batch][n_focus][n][n].
  * For each plane and kernel the coherent field E_k is recomputed (never
  * stored) and correlated with G through the conjugate kernel:
@@ -201,6 +215,123 @@ int litho_image_grad(const litho_bank_t *bank, const float *d_mask, int batch, i
                      const float *d_target, const litho_resist_t *resist,
                      const float *d_grad_image, float *d_image, double *d_loss,
                      float *d_grad_mask, int prec, void *hip_stream);
+
+/* ---------------------------------------------------------------- after the image
+ * The steps that follow the aerial image in the paper's flow: the resist
+ * kernel and the target low-pass (Gaussian filters, Eqs. 5 and 16), the
+ * printed contour (the level set of Eq. 5, extracted by marching squares as
+ * in Sec. II-D), the edge placement error through focus (Eqs. 6-8) and the
+ * physics channels of the AI initialiser's input (Eq. 9). */
+
+/* Periodic Gaussian low-pass of count real images [count][n][n] (n = the
+ * bank's grid side; the bank supplies the transform tables and workspace):
+ *   out = Re IDFT( DFT(in) * exp(-2 pi^2 s^2 (fx^2 + fy^2) / n^2) ),
+ * the transfer function truncated where it falls below 1e-12, at
+ * |fx|, |fy| <= h = min(n/2 - 1, ceil(1.1832 n / s)).  This is Eq. 5's resist
+ * kernel K_resist applied to an image (exact to that truncation for an aerial
+ * image, which is band-limited to |f| <= 2b) and Eq. 16's G_sigma.
+ * threshold: NaN for the filtered values; otherwise out = 1 where the
+ * filtered value is >= threshold, else 0 (Eq. 16's Z_round with
+ * tau_round = threshold).  d_in and d_out may be the same array.
+ * Errors: LITHO_E_INVALID (NULL pointers, sigma_px <= 0).  Asynchronous. */
+int litho_lowpass(const litho_bank_t *bank, const float *d_in, int count, double sigma_px,
+                  double threshold, float *d_out, void *hip_stream);
+
+/* Marching-squares contours of one periodic image at `level` (Sec. II-D; the
+ * contour C of Eq. 5 when the image is the resist image and level = T_eff).
+ * Cell (y, x), 0 <= y, x < n, has corners v(y,x), v(y,x+1), v(y+1,x+1),
+ * v(y+1,x) (indices mod n); a corner is inside when v >= level (float32).
+ * Edges: 0 top, 1 right, 2 bottom, 3 left.  A cell with one or three inside
+ * corners, or two adjacent ones, holds one segment; two diagonal inside
+ * corners (a saddle) hold two, joined as the cell mean 0.25 ((c0 + c1) +
+ * (c2 + c3)) >= level decides (centre inside or not).  Segments run with the
+ * inside on their left (x to the right, y down) and are listed in raster
+ * order of cells, then by start edge.  Per segment j < capacity:
+ *   d_cell[j]  = y * n + x;
+ *   d_code[j]  = start_edge * 4 + end_edge;
+ *   d_u[2j], d_u[2j+1] = crossing parameters on the start and end edge,
+ *                (level - a) / (b - a) from the edge's first corner a (left
+ *                end of a horizontal edge, top end of a vertical one);
+ *   d_next[j]  = index of the segment that starts where segment j ends (the
+ *                segments form closed loops; indices may reach past capacity).
+ * d_count (device int) receives the total number of segments; when it
+ * exceeds capacity only the first capacity segments were written and the
+ * call can be repeated with a larger capacity.  capacity 0 counts only (the
+ * output pointers may then be NULL).  The library keeps count/offset scratch
+ * of 2 n ceil(n/64) + 1 ints per device and stream.  2 <= n <= 4096
+ * (LITHO_E_UNSUPPORTED otherwise).  Asynchronous. */
+int litho_contours(int n, const float *d_image, double level, int capacity, int *d_cell, int *d_code,
+                   float *d_u, int *d_next, int *d_count, void *hip_stream);
+
+/* Eq. 6's target level and Eq. 8's through-focus rule. */
+typedef struct litho_epe_rule {
+  double t_eff;     /* E_tgt on the target edge (the printing threshold) */
+  double tol_neg;   /* tol_neg <= 0 */
+  double tol_pos;   /* tol_pos >= 0 */
+  int f0;           /* index of the on-focus plane among the latent images */
+} litho_epe_rule_t;
+
+/* Edge placement error at the edges of a binary target through focus
+ * (Eqs. 6-8).  Sites are the 4-neighbour pixel pairs whose targets
+ * (T >= 0.5) differ, listed per pixel (y, x) in raster order: first the pair
+ * with (y, x+1), then with (y+1, x) (periodic).  At a site, for each latent
+ * image E_p (d_latent [n_planes][n][n], e.g. the resist image of each focus
+ * plane) the iso-level E = t_eff is located by Eq. 6 at the pair's midpoint:
+ *   EPE_p = -(E_mid - t_eff) / |grad E|,  E_mid = (E_a + E_b) / 2,
+ * with the normal derivative E_b - E_a and the tangential derivative a
+ * quarter of the difference of the neighbouring pairs' sums on either side
+ * (pixels; +-inf where the gradient vanishes, 0 if E_mid = t_eff too).  Per
+ * site j < capacity: d_site[j] = y * n + x, d_dir[j] = 0 (pair along x) or
+ * 1 (along y), d_epe[j][0 .. n_planes-1] = EPE_p, d_epe[j][n_planes] =
+ * EPE_avg (Eq. 7), d_epe[j][n_planes+1] = EPE_eff (Eq. 8: EPE_f0 - tol_pos
+ * above tol_pos, EPE_f0 - tol_neg below tol_neg, EPE_avg between, bounds
+ * included).  Arithmetic in float32.  d_count and capacity as for
+ * litho_contours; 1 <= n_planes <= 8.  Asynchronous. */
+int litho_epe(int n, const float *d_target, const float *d_latent, int n_planes, const litho_epe_rule_t *rule,
+              int capacity, int *d_site, int *d_dir, float *d_epe, int *d_count, void *hip_stream);
+
+/* The three input channels of Eq. 9 for a batch of target layouts Z_t
+ * (d_layout [batch][n][n]), channel last: d_out[batch][n][n][3] =
+ *   (M0 = Z_t,  I0 = the SOCS image of Z_t at focus plane `plane` with K_use
+ *    kernels (Eq. 4),  dI/dM = dI(r)/dm(r), the image's derivative with
+ *    respect to the mask pixel at the same position,
+ *    2 D sum_k lambda_k Re[ conj(E_k(r)) phi_k(0) ], phi_k(0) = IDFT(Phi_k)(0)).
+ * h_norm: NULL (raw values) or [6] = (lo, hi) per channel; each channel is
+ * then mapped to clip((v - lo) / (hi - lo), 0, 1) (the global normalisation
+ * of Eq. 9).  Asynchronous. */
+int litho_ai_channels(const litho_bank_t *bank, const float *d_layout, int batch, int K_use, int plane,
+                      const double *h_norm, float *d_out, void *hip_stream);
+
+/* ---------------------------------------------------------------- layouts beyond one clip
+ * A layout larger than a clip (the paper's flow images full layouts; it does
+ * not describe its tiling) is imaged through halo tiling with the bank's clip
+ * side n: the H x W layout (row-major, opaque outside: m = 0) is cut into
+ * n x n windows with a halo of `halo` pixels around a core of
+ * c = n - 2 halo pixels; core (i, j) starts at (i c, j c) and its window at
+ * (i c - halo, j c - halo), ceil(H / c) x ceil(W / c) tiles in raster order.
+ * Each window is imaged as one periodic clip (Eq. 4, every focus plane of the
+ * bank) and the image of its core is kept, so the halo must cover the
+ * optical ambit for the seams to vanish.  Windows are processed in chunks
+ * that fit the workspace limit.  Errors: LITHO_E_INVALID (NULL pointers, no
+ * core left: n - 2 halo < 1, H or W < 1).  Asynchronous. */
+
+/* d_layout [H][W]; d_image [n_focus][H][W]. */
+int litho_image_tiled(const litho_bank_t *bank, const float *d_layout, int H, int W, int halo, int K_use,
+                      float *d_image, int prec, void *hip_stream);
+
+/* Tiled ILT loss and gradient: L = sum_p w_p sum over layout pixels of
+ * (Z - T)^2 (|Z - T| for LITHO_LOSS_L1) with Z the sigmoid resist of the
+ * tiled image (each layout pixel counted once, in its core), and dL/dm, the
+ * exact derivative of that tiled loss: per window, the adjoint of
+ * litho_image_grad with the residual restricted to the core, summed into
+ * the layout gradient over the whole window in tile order (deterministic).
+ * d_target [H][W]; resist: slope, threshold, plane weights and loss as for
+ * litho_image_grad (blur_sigma_px must be 0: LITHO_E_UNSUPPORTED otherwise);
+ * d_image [n_focus][H][W] or NULL; d_loss: device double [1] or NULL;
+ * d_grad [H][W]. */
+int litho_image_grad_tiled(const litho_bank_t *bank, const float *d_layout, int H, int W, int halo, int K_use,
+                           const float *d_target, const litho_resist_t *resist, float *d_image, double *d_loss,
+                           float *d_grad, int prec, void *hip_stream);
 
 /* Per-kernel device timing (tracing).  While enabled, every kernel launch is
  * bracketed by HIP events on its own stream; litho_profile_read() waits for

@@ -52,8 +52,17 @@ class BankInfo(C.Structure):
     ]
 
 
+LITHO_LOSS_L2 = 0
+LITHO_LOSS_L1 = 1
+
+
 class Resist(C.Structure):
-    _fields_ = [("slope", C.c_double), ("threshold", C.c_double), ("plane_weight", C.POINTER(C.c_double))]
+    _fields_ = [("slope", C.c_double), ("threshold", C.c_double), ("plane_weight", C.POINTER(C.c_double)),
+                ("blur_sigma_px", C.c_double), ("loss", C.c_int)]
+
+
+class EpeRule(C.Structure):
+    _fields_ = [("t_eff", C.c_double), ("tol_neg", C.c_double), ("tol_pos", C.c_double), ("f0", C.c_int)]
 
 
 class ServeCfg(C.Structure):
@@ -92,6 +101,13 @@ SIGNATURES = {
     "litho_image": (C.c_int, [VP, VP, C.c_int, C.c_int, VP, C.c_int, VP]),
     "litho_image_grad": (C.c_int, [VP, VP, C.c_int, C.c_int, VP, C.POINTER(Resist), VP, VP, VP, VP,
                                    C.c_int, VP]),
+    "litho_lowpass": (C.c_int, [VP, VP, C.c_int, C.c_double, C.c_double, VP, VP]),
+    "litho_contours": (C.c_int, [C.c_int, VP, C.c_double, C.c_int, VP, VP, VP, VP, VP, VP]),
+    "litho_epe": (C.c_int, [C.c_int, VP, VP, C.c_int, C.POINTER(EpeRule), C.c_int, VP, VP, VP, VP, VP]),
+    "litho_ai_channels": (C.c_int, [VP, VP, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), VP, VP]),
+    "litho_image_tiled": (C.c_int, [VP, VP, C.c_int, C.c_int, C.c_int, C.c_int, VP, C.c_int, VP]),
+    "litho_image_grad_tiled": (C.c_int, [VP, VP, C.c_int, C.c_int, C.c_int, C.c_int, VP, C.POINTER(Resist), VP, VP,
+                                         VP, C.c_int, VP]),
     "litho_profile_enable": (C.c_int, [C.c_int]),
     "litho_profile_read": (C.c_int, [C.c_char_p, C.c_size_t]),
     "litho_serve_create": (C.c_int, [C.POINTER(VP), C.c_int, C.POINTER(ServeCfg), C.POINTER(VP)]),

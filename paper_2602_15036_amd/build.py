@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblitho.so")
 
-SOURCES = ["kernels.hip", "api.cpp", "bank.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "bank.cpp", "serve.cpp", "post.hip", "post_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

@@ -16,6 +16,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "litho_internal.hpp"
+#include "post.hpp"
 
 // ============================================================ errors
 namespace litho {
@@ -351,8 +352,15 @@ extern "C" int litho_kernels_phi(const litho_bank_t *bk, int plane, int k, doubl
 extern "C" void litho_kernels_free(litho_bank_t *bk) {
   if (!bk) return;
   (void)hipDeviceSynchronize();
-  for (auto &kv : bk->ws)
+  for (auto &kv : bk->ws) {
     if (kv.second.base) (void)hipFree(kv.second.base);
+    for (hipStream_t t : kv.second.side) (void)hipStreamDestroy(t);
+    for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
+  }
+  for (auto &kv : bk->aux)
+    if (kv.second.base) (void)hipFree(kv.second.base);
+  for (auto &kv : bk->psi)
+    if (kv.second) (void)hipFree(kv.second);
   if (bk->d_twQ && bk->d_twQ != bk->d_twN) (void)hipFree(bk->d_twQ);
   for (void *t : bk->d_gemm)
     if (t) (void)hipFree(t);
@@ -373,7 +381,7 @@ size_t workspace_limit_bytes() {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool fused, int prec) {
+CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool fused, int prec, bool blur) {
   CallLayout L;
   const HostBank &h = bk->host;
   PassGeo &g = L.g;
@@ -396,7 +404,10 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
     g.kper = (K_use + kc - 1) / kc;
     g.KC = (K_use + g.kper - 1) / g.kper;
   }
-  const bool resample = g.Q != g.N;
+  // a resist blur acts on the intensity band, so it takes the resampling route
+  // even when the per-kernel transforms run on the full grid
+  const bool resample = g.Q != g.N || (blur && fused && grad);
+  L.resample = resample;
   // loss partials come from the row pass that applies the resist (N grid):
   // one per block; with resampling that pass takes two rows per transform
   L.nblk = resample ? (g.N / (256 / pass_threads(g.N)) + 1) / 2 : g.N / (256 / pass_threads(g.N));
@@ -408,16 +419,25 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
   L.b_part = grad ? align256(size_t(g.P) * g.KC * g.nt * g.B * kTileCols * sizeof(double2)) : 0;
   L.b_loss = (grad && fused) ? align256(size_t(g.P) * L.nblk * sizeof(double)) : 0;
   L.b_X = resample ? align256(std::max(N, Q) * g.Dp * sizeof(float2)) : 0;
-  const size_t per = L.b_S1 + L.b_Mh + L.b_Y + L.b_G + L.b_part + L.b_loss + 2 * L.b_X;
+  // Few clips and several focus planes: the per-kernel passes of one plane
+  // launch too few workgroups to fill the device, so the planes run
+  // concurrently on side streams, each with its own Y, G and band buffers.
+  // Row passes launch about Q / (256 / T) workgroups per clip.
+  {
+    const size_t row_blocks = size_t(Q) / (256 / pass_threads(g.Q)) * size_t(batch);
+    L.pp = (g.P > 1 && row_blocks < 2048) ? g.P : 1;
+  }
+  const size_t per = L.b_S1 + L.b_Mh + L.b_part + L.b_loss + size_t(L.pp) * (L.b_Y + L.b_G + 2 * L.b_X);
   L.per_clip = per;
   const size_t lim = workspace_limit_bytes();
   L.chunk = int(std::max<size_t>(1, std::min<size_t>(size_t(batch), lim / per)));
   return L;
 }
 
-int acquire_workspace(litho_bank *bk, hipStream_t s, size_t bytes, char **out) {
+static int grow_workspace(litho_bank *bk, std::map<hipStream_t, Workspace> &m, hipStream_t s, size_t bytes,
+                          char **out) {
   std::lock_guard<std::mutex> lk(bk->mu);
-  Workspace &w = bk->ws[s];
+  Workspace &w = m[s];
   if (w.bytes < bytes) {
     if (w.base) {
       LITHO_HIP_TRY(hipStreamSynchronize(s));
@@ -437,38 +457,84 @@ int acquire_workspace(litho_bank *bk, hipStream_t s, size_t bytes, char **out) {
   return LITHO_OK;
 }
 
+int acquire_workspace(litho_bank *bk, hipStream_t s, size_t bytes, char **out) {
+  return grow_workspace(bk, bk->ws, s, bytes, out);
+}
+
+int acquire_aux(litho_bank *bk, hipStream_t s, size_t bytes, char **out) {
+  return grow_workspace(bk, bk->aux, s, bytes, out);
+}
+
+// count side streams of the workspace of stream s, and count + 1 events.
+int plane_streams(litho_bank *bk, hipStream_t s, int count, hipStream_t *side, hipEvent_t *ev) {
+  std::lock_guard<std::mutex> lk(bk->mu);
+  Workspace &w = bk->ws[s];
+  while (int(w.side.size()) < count) {
+    hipStream_t t = nullptr;
+    LITHO_HIP_TRY(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+    w.side.push_back(t);
+  }
+  while (int(w.ev.size()) < count + 1) {
+    hipEvent_t e = nullptr;
+    LITHO_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    w.ev.push_back(e);
+  }
+  for (int i = 0; i < count; ++i) side[i] = w.side[i];
+  for (int i = 0; i <= count; ++i) ev[i] = w.ev[i];
+  return LITHO_OK;
+}
+
 // Forward (and optionally adjoint) over one chunk of clips.
 int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, int n, const float *target,
               const float *grad_image, float *image, double *loss, float *grad_mask, bool grad, hipStream_t s,
-              double slope, double thr, const double *plane_w, int prec, const void *gemm_fwd,
-              const void *gemm_adj) {
+              const CallOpts &o, int prec, const void *gemm_fwd, const void *gemm_adj) {
   PassGeo g = L.g;
-  g.slope = slope;
-  g.thr = thr;
+  g.slope = o.slope;
+  g.thr = o.thr;
+  g.loss_l1 = o.loss_l1;
+  const double *plane_w = o.plane_w;
   char *p = ws;
   auto *S1 = reinterpret_cast<float2 *>(p); p += L.b_S1 * n;
   auto *Mh = reinterpret_cast<float2 *>(p); p += L.b_Mh * n;
-  auto *Y = reinterpret_cast<float2 *>(p); p += L.b_Y * n;
-  auto *G = reinterpret_cast<float *>(p); p += L.b_G * n;
   auto *part = reinterpret_cast<double2 *>(p); p += L.b_part * n;
   auto *lossp = reinterpret_cast<double *>(p); p += L.b_loss * n;
-  auto *X1 = reinterpret_cast<float2 *>(p); p += L.b_X * n;
-  auto *X2 = reinterpret_cast<float2 *>(p);
+  // per concurrent plane: Y, G, X1, X2
+  char *const plane_base = p;
+  const size_t plane_bytes = (L.b_Y + L.b_G + 2 * L.b_X) * n;
+  hipStream_t side[8] = {};
+  hipEvent_t ev[9] = {};
+  if (L.pp > 1) LITHO_TRY(plane_streams(bk, s, L.pp - 1, side, ev));
   const bool fused = target != nullptr;
-  const bool resample = g.Q != g.N;
+  const bool resample = L.resample;
+  const double blur = fused && grad ? o.blur_sigma : 0.0;
   const size_t NN = size_t(g.N) * g.N;
+  const size_t band_clip = size_t(g.ntD) * g.D * kTileCols;  // complex values of one D x D band
   const int h2 = 2 * g.b;
   const float2 *twN = bk->d_twN, *twQ = bk->d_twQ;
   // mask spectrum (once per clip, shared by every plane)
   LITHO_TRY(run_rows_fwd_real("mask_rows", g.N, mask, NN, S1, g.b, g.Bp, twN,
                               float(1.0 / (double(g.N) * double(g.N))), n, s));
   LITHO_TRY(run_col_fft("mask_cols", g.N, -1, S1, Mh, g.nt, -1, g.b, twN, 1.0f, n, s));
-  EpiPtrs ep;
-  ep.image = image;
-  ep.target = grad && fused ? target : nullptr;
-  ep.G = G;
-  ep.loss_part = lossp;
-  for (int pl = 0; pl < g.P; ++pl) {
+  const int p_end = o.p1 < 0 ? g.P : std::min(g.P, o.p1);
+  if (L.pp > 1) {
+    // fork: the side streams start after the mask spectrum
+    LITHO_HIP_TRY(hipEventRecord(ev[0], s));
+    for (int i = 0; i < L.pp - 1; ++i) LITHO_HIP_TRY(hipStreamWaitEvent(side[i], ev[0], 0));
+  }
+  const hipStream_t s_main = s;
+  for (int pl = o.p0; pl < p_end; ++pl) {
+    const int slot = L.pp > 1 ? pl % L.pp : 0;
+    char *q = plane_base + size_t(slot) * plane_bytes;
+    auto *Y = reinterpret_cast<float2 *>(q); q += L.b_Y * n;
+    auto *G = reinterpret_cast<float *>(q); q += L.b_G * n;
+    auto *X1 = reinterpret_cast<float2 *>(q); q += L.b_X * n;
+    auto *X2 = reinterpret_cast<float2 *>(q);
+    const hipStream_t s = slot == 0 ? s_main : side[slot - 1];
+    EpiPtrs ep;
+    ep.image = image;
+    ep.target = grad && fused ? target : nullptr;
+    ep.G = G;
+    ep.loss_part = lossp;
     g.p = pl;
     g.pw = plane_w ? plane_w[pl] : 1.0;
     if (prec == LITHO_PREC_FP32)
@@ -480,6 +546,8 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
     } else {
       LITHO_TRY(run_pass_x_fwd(Y, EpiPtrs{}, X1, g, twQ, n, s));
       LITHO_TRY(run_col_fft("up_cols_q", g.Q, -1, X1, X2, g.ntD, -1, h2, twQ, 1.0f, n, s));
+      // resist kernel of Eq. 5 on the intensity band: R = I (x) K_resist
+      LITHO_TRY(run_band_gauss(X2, h2, g.ntD, double(g.N), blur, band_clip, n, s));
       LITHO_TRY(run_col_fft("up_cols_n", g.N, +1, X2, X1, g.ntD, h2, -1, twN, 1.0f, n, s));
       if (ep.image || ep.target)
         LITHO_TRY(run_rows_inv_real("up_rows", g.N, X1, h2, g.Dp, nullptr, ep, g, twN, 1.0f, n, s));
@@ -493,6 +561,8 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
       // G low-passed to |f| <= 2b and sampled on the Q grid (scaled by 1/Q^2)
       LITHO_TRY(run_rows_fwd_real("down_rows", g.N, Gp, gstride, X1, h2, g.Dp, twN, 1.0f, n, s));
       LITHO_TRY(run_col_fft("down_cols_n", g.N, -1, X1, X2, g.ntD, -1, h2, twN, 1.0f, n, s));
+      // dL/dI = K_resist (x) dL/dR (the Gaussian is symmetric)
+      LITHO_TRY(run_band_gauss(X2, h2, g.ntD, double(g.N), blur, band_clip, n, s));
       LITHO_TRY(run_col_fft("down_cols_q", g.Q, +1, X2, X1, g.ntD, h2, -1, twQ,
                             float(1.0 / (double(g.Q) * double(g.Q))), n, s));
       LITHO_TRY(run_pass_x_adj(Y, nullptr, 0, X1, g, twQ, n, s));
@@ -501,6 +571,13 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
       LITHO_TRY(run_pass_y_adj(Y, bk->d_phi, part, g, twQ, n, s));
     else
       LITHO_TRY(run_pass_y_adj_mfma(Y, bk->d_phi, part, g, gemm_adj, prec, n, s));
+  }
+  if (L.pp > 1) {
+    // join: the call's stream waits for every side stream
+    for (int i = 0; i < L.pp - 1; ++i) {
+      LITHO_HIP_TRY(hipEventRecord(ev[1 + i], side[i]));
+      LITHO_HIP_TRY(hipStreamWaitEvent(s_main, ev[1 + i], 0));
+    }
   }
   if (grad) {
     LITHO_TRY(run_grad_cols(part, g.P * g.KC, S1, g, twN, n, s));
@@ -539,16 +616,26 @@ namespace litho {
 // so the kernels see dense per-clip arrays.  run_chunk() expects exactly that.
 int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, const float *d_target,
                     const litho_resist_t *resist, const float *d_grad_image, float *d_image, double *d_loss,
-                    float *d_grad_mask, bool grad, int prec, hipStream_t s) {
+                    float *d_grad_mask, bool grad, int prec, hipStream_t s, int p0, int p1) {
   if (batch == 0) return LITHO_OK;
   const bool fused = d_target != nullptr;
+  CallOpts o;
+  if (resist) {
+    o.slope = resist->slope;
+    o.thr = resist->threshold;
+    o.plane_w = resist->plane_weight;
+    o.blur_sigma = resist->blur_sigma_px;
+    o.loss_l1 = resist->loss == LITHO_LOSS_L1 ? 1 : 0;
+  }
+  o.p0 = p0;
+  o.p1 = p1;
   const void *gemm_fwd = nullptr, *gemm_adj = nullptr;
   if (prec != LITHO_PREC_FP32) {
     const bool bf = prec == LITHO_PREC_BF16X3 || prec == LITHO_PREC_BF16;
     LITHO_TRY(gemm_table(bk, false, bf, &gemm_fwd));
     if (grad) LITHO_TRY(gemm_table(bk, true, bf, &gemm_adj));
   }
-  CallLayout L = plan_call(bk, batch, K_use, grad, fused, prec);
+  CallLayout L = plan_call(bk, batch, K_use, grad, fused, prec, o.blur_sigma > 0.0);
   char *ws = nullptr;
   LITHO_TRY(acquire_workspace(bk, s, L.per_clip * size_t(L.chunk), &ws));
   const size_t NN = size_t(bk->host.n) * bk->host.n;
@@ -558,9 +645,8 @@ int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, c
     LITHO_TRY(run_chunk(bk, L, ws, d_mask + size_t(c0) * NN, n, fused ? d_target + size_t(c0) * NN : nullptr,
                         d_grad_image ? d_grad_image + size_t(c0) * P * NN : nullptr,
                         d_image ? d_image + size_t(c0) * P * NN : nullptr, d_loss ? d_loss + c0 : nullptr,
-                        d_grad_mask ? d_grad_mask + size_t(c0) * NN : nullptr, grad, s,
-                        resist ? resist->slope : 0.0, resist ? resist->threshold : 0.0,
-                        resist ? resist->plane_weight : nullptr, prec, gemm_fwd, gemm_adj));
+                        d_grad_mask ? d_grad_mask + size_t(c0) * NN : nullptr, grad, s, o, prec, gemm_fwd,
+                        gemm_adj));
   }
   return LITHO_OK;
 }

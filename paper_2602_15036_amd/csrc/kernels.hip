@@ -68,6 +68,7 @@ struct Geo {
   float dose;
   float slope, thr;
   float pw;   // weight of the current plane's loss
+  int loss_l1;  // 1: |Z - T| loss, 0: (Z - T)^2
 };
 
 // Outputs of the image epilogue (image, resist, loss, residual).
@@ -305,6 +306,17 @@ __device__ __forceinline__ double image_epilogue_row(const Epi &ep, const Geo &g
   if (!ep.target) return 0.0;
   float *G = ep.G + size_t(clip) * NN + ro;
   double l = 0.0;
+  if (g.loss_l1) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const float z = 1.0f / (1.0f + expf(-g.slope * (I[i] - g.thr)));
+      const float d = z - tg[i];
+      const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+      G[T * i] = g.pw * sg * g.slope * z * (1.0f - z);
+      l += double(g.pw) * double(fabsf(d));
+    }
+    return l;
+  }
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const float z = 1.0f / (1.0f + expf(-g.slope * (I[i] - g.thr)));
@@ -363,6 +375,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd_real(const float *__restrict__
 
 // ------------------------------------------------------------ band rows -> real rows
 // v = sum_kx in(y, kx) exp(+2 pi i kx x / L); MODE 0: out[y][x] = scale Re v;
+// MODE 2: out[y][x] = 1 where scale Re v >= g.thr, else 0;
 // MODE 1: I = scale Re v through the image / resist epilogue (L == N).  The
 // image rows are real, so their band rows are Hermitian and MODE 1 sends two
 // rows through one complex transform: X_y0 + i X_y1 yields row y0 in the real
@@ -377,13 +390,18 @@ __global__ __launch_bounds__(256) void k_rows_inv_real(const cf *__restrict__ in
   const int clip = blockIdx.y;
   const cf *src = in + size_t(clip) * (Wp / kC) * L * kC;
   cf v[E];
-  if constexpr (MODE == 0) {
+  if constexpr (MODE != 1) {
     const int y = blockIdx.x * RPB + row;
     load_band_row_v<L, T, PR>(v, src, unsigned(size_t(Wp) * L * sizeof(cf)), y, t, h);
     fft<L, +1>(v, smem + row * lds_len<L>(), t, tw);
     float *dst = out + (size_t(clip) * L + y) * L;
+    if constexpr (MODE == 0) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) dst[t + T * i] = scale * v[i].x;
+      for (int i = 0; i < E; ++i) dst[t + T * i] = scale * v[i].x;
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) dst[t + T * i] = scale * v[i].x >= g.thr ? 1.0f : 0.0f;
+    }
   } else {
     // a block past the last pair (L / RPB odd) recomputes it and stores nothing
     const int yp = 2 * (blockIdx.x * RPB + row);
@@ -1226,6 +1244,7 @@ Geo to_geo(const PassGeo &pg) {
   g.D = pg.D; g.Dp = pg.Dp; g.ntD = pg.ntD;
   g.K = pg.K; g.Kbank = pg.Kbank; g.P = pg.P; g.p = pg.p; g.KC = pg.KC; g.kper = pg.kper;
   g.dose = float(pg.dose); g.slope = float(pg.slope); g.thr = float(pg.thr); g.pw = float(pg.pw);
+  g.loss_l1 = pg.loss_l1;
   return g;
 }
 
@@ -1349,7 +1368,7 @@ int pass_x_fwd_q(const cf *Y, const EpiPtrs &ep, cf *Ib, const PassGeo &pg, cons
   constexpr int T = FftPlan<Q>::T, RPB = 256 / T;
   Geo g = to_geo(pg);
   Epi e = to_epi(ep);
-  const bool band = g.Q != g.N;
+  const bool band = Ib != nullptr;
   size_t sh = size_t(RPB) * lds_len<Q>() * sizeof(cf);
   sh = std::max(sh, size_t(256) * sizeof(double)) + dev::TwLds<Q>::bytes;
   const bool pr = dev::prunable<Q>(g.b);
@@ -1583,6 +1602,13 @@ int run_rows_inv_real(const char *name, int L, const cf2 *in, int h, int Wp, flo
   }
   LITHO_DISPATCH_N(L, (rows_inv_real_l<NN, 0>(name, (const cf *)in, h, Wp, out, ep, g, (const cf *)tw, scale,
                                                nclips, s)));
+}
+int run_rows_inv_thresh(const char *name, int L, const cf2 *in, int h, int Wp, float *out, double thr,
+                        const cf2 *tw, float scale, int nclips, hipStream_t s) {
+  PassGeo g;
+  g.thr = thr;
+  LITHO_DISPATCH_N(L, (rows_inv_real_l<NN, 2>(name, (const cf *)in, h, Wp, out, EpiPtrs{}, g, (const cf *)tw,
+                                               scale, nclips, s)));
 }
 int run_col_fft(const char *name, int L, int dir, const cf2 *in, cf2 *out, int nt, int in_h, int out_h,
                 const cf2 *tw, float scale, int nclips, hipStream_t s) {

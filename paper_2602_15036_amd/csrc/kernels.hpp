@@ -25,6 +25,7 @@ struct PassGeo {
   int KC = 1, kper = 1;  // k-chunks of the adjoint column pass
   double dose = 1.0, slope = 0.0, thr = 0.0;
   double pw = 1.0;       // weight of the current plane's loss
+  int loss_l1 = 0;       // 1: |Z - T| loss, 0: (Z - T)^2
 };
 
 // Outputs of the image epilogue.
@@ -50,6 +51,9 @@ int run_rows_fwd_real(const char *name, int L, const float *in, size_t in_clip, 
                       const cf2 *tw, float scale, int nclips, hipStream_t s);
 int run_rows_inv_real(const char *name, int L, const cf2 *in, int h, int Wp, float *out, const EpiPtrs &ep,
                       const PassGeo &g, const cf2 *tw, float scale, int nclips, hipStream_t s);
+// Same as run_rows_inv_real without epilogue, written as 1 where scale Re v >= thr, else 0.
+int run_rows_inv_thresh(const char *name, int L, const cf2 *in, int h, int Wp, float *out, double thr,
+                        const cf2 *tw, float scale, int nclips, hipStream_t s);
 int run_col_fft(const char *name, int L, int dir, const cf2 *in, cf2 *out, int nt, int in_h, int out_h,
                 const cf2 *tw, float scale, int nclips, hipStream_t s);
 int run_pass_y_fwd(const cf2 *bank, const cf2 *Mh, cf2 *Y, const PassGeo &g, const cf2 *twQ, int nclips,

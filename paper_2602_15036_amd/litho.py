@@ -183,13 +183,18 @@ def image(bank: Bank, mask: torch.Tensor, K_use: Optional[int] = None,
     return out
 
 
+LOSS_KINDS = {"l2": A.LITHO_LOSS_L2, "l1": A.LITHO_LOSS_L1}
+
+
 def image_grad(bank: Bank, mask: torch.Tensor, target: Optional[torch.Tensor] = None,
                slope: float = 50.0, threshold: float = 0.3, grad_image: Optional[torch.Tensor] = None,
                K_use: Optional[int] = None, want_image: bool = True, stream=None, prec="fp32",
-               plane_weights: Optional[Sequence[float]] = None):
-    """Image, loss and mask gradient (fused sigmoid-L2 loss) or a VJP with dL/dI.
+               plane_weights: Optional[Sequence[float]] = None, blur_sigma_px: float = 0.0, loss: str = "l2"):
+    """Image, loss and mask gradient (fused sigmoid loss) or a VJP with dL/dI.
 
     plane_weights: loss weight of each focus plane (fused mode; default 1 each).
+    blur_sigma_px: Gaussian resist kernel (fused mode; the image output is then
+    the blurred resist image).  loss: "l2" or "l1" (fused mode).
     Returns (image or None, loss [batch] float64 or None, grad [batch, n, n]).
     """
     mask = _mask_batch(mask, bank.n)
@@ -199,6 +204,7 @@ def image_grad(bank: Bank, mask: torch.Tensor, target: Optional[torch.Tensor] = 
     img = torch.empty((batch, bank.n_focus, bank.n, bank.n), device=dev, dtype=torch.float32) \
         if want_image else None
     grad = torch.empty((batch, bank.n, bank.n), device=dev, dtype=torch.float32)
+    loss_kind = LOSS_KINDS[loss]
     loss = None
     resist = None
     if target is not None:
@@ -210,7 +216,8 @@ def image_grad(bank: Bank, mask: torch.Tensor, target: Optional[torch.Tensor] = 
                 raise ValueError(f"plane_weights needs {bank.n_focus} values")
             pw = (C.c_double * bank.n_focus)(*[float(v) for v in plane_weights])
         resist = A.Resist(slope=slope, threshold=threshold,
-                          plane_weight=None if pw is None else C.cast(pw, C.POINTER(C.c_double)))
+                          plane_weight=None if pw is None else C.cast(pw, C.POINTER(C.c_double)),
+                          blur_sigma_px=float(blur_sigma_px), loss=loss_kind)
     if grad_image is not None and grad_image.shape != (batch, bank.n_focus, bank.n, bank.n):
         raise ValueError("grad_image must be [batch, n_focus, n, n]")
     _check(_lib.litho_image_grad(
@@ -219,6 +226,138 @@ def image_grad(bank: Bank, mask: torch.Tensor, target: Optional[torch.Tensor] = 
         _dev_ptr(img, "image"), _dev_ptr(loss, "loss", torch.float64), _dev_ptr(grad, "grad"),
         prec_code(prec), C.c_void_p(_stream_handle(stream))), "litho_image_grad")
     return img, loss, grad
+
+
+def lowpass(bank: Bank, images: torch.Tensor, sigma_px: float, threshold: Optional[float] = None,
+            out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Gaussian low-pass of [count, n, n] images (K_resist of Eq. 5, G_sigma of
+    Eq. 16); with a threshold the 0/1 image of filtered >= threshold."""
+    images = _mask_batch(images, bank.n)
+    if out is None:
+        out = torch.empty_like(images)
+    thr = float("nan") if threshold is None else float(threshold)
+    _check(_lib.litho_lowpass(bank.handle, _dev_ptr(images, "images"), images.shape[0], float(sigma_px), thr,
+                              _dev_ptr(out, "out"), C.c_void_p(_stream_handle(stream))), "litho_lowpass")
+    return out
+
+
+def _compaction(call, capacity, what, stream):
+    """Runs a counting call, then the filling call with enough capacity."""
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    if capacity is None:
+        _check(call(0, count), what)
+        capacity = int(count.item())
+    _check(call(capacity, count), what)
+    total = int(count.item())
+    if total > capacity:
+        _check(call(total, count), what)
+    return total
+
+
+def contours(image: torch.Tensor, level: float, capacity: Optional[int] = None, stream=None) -> dict:
+    """Marching-squares contour segments of one [n, n] image at `level`
+    (litho_contours): dict of cell, code (start * 4 + end), u [S, 2], next."""
+    if image.dim() != 2 or image.shape[0] != image.shape[1]:
+        raise ValueError("image must be [n, n]")
+    n = image.shape[0]
+    bufs = {}
+
+    def call(cap, count):
+        for k, shape, dt in (("cell", (cap,), torch.int32), ("code", (cap,), torch.int32),
+                             ("u", (cap, 2), torch.float32), ("next", (cap,), torch.int32)):
+            if k not in bufs or bufs[k].shape[0] < cap:
+                bufs[k] = torch.empty(shape, dtype=dt, device=image.device)
+        return _lib.litho_contours(n, _dev_ptr(image, "image"), float(level), cap,
+                                   _addr(bufs["cell"], "cell", torch.int32), _addr(bufs["code"], "code", torch.int32),
+                                   _addr(bufs["u"], "u"), _addr(bufs["next"], "next", torch.int32),
+                                   _addr(count, "count", torch.int32), C.c_void_p(_stream_handle(stream)))
+    total = _compaction(call, capacity, "litho_contours", stream)
+    return {k: v[:total] for k, v in bufs.items()}
+
+
+def epe(target: torch.Tensor, latent: torch.Tensor, t_eff: float, f0: int = 0, tol_neg: float = 0.0,
+        tol_pos: float = 0.0, capacity: Optional[int] = None, stream=None) -> dict:
+    """Edge placement error through focus (litho_epe) at the edge sites of a
+    binary target [n, n] for latent images [P, n, n]: dict of site (y * n + x),
+    dir (0 along x, 1 along y) and epe [S, P + 2] (per plane, average, effective)."""
+    n = target.shape[-1]
+    if latent.dim() == 2:
+        latent = latent[None]
+    P = latent.shape[0]
+    rule = A.EpeRule(t_eff=float(t_eff), tol_neg=float(tol_neg), tol_pos=float(tol_pos), f0=int(f0))
+    bufs = {}
+
+    def call(cap, count):
+        for k, shape, dt in (("site", (cap,), torch.int32), ("dir", (cap,), torch.int32),
+                             ("epe", (cap, P + 2), torch.float32)):
+            if k not in bufs or bufs[k].shape[0] < cap:
+                bufs[k] = torch.empty(shape, dtype=dt, device=target.device)
+        return _lib.litho_epe(n, _dev_ptr(target, "target"), _dev_ptr(latent, "latent"), P, C.byref(rule), cap,
+                              _addr(bufs["site"], "site", torch.int32), _addr(bufs["dir"], "dir", torch.int32),
+                              _addr(bufs["epe"], "epe"), _addr(count, "count", torch.int32),
+                              C.c_void_p(_stream_handle(stream)))
+    total = _compaction(call, capacity, "litho_epe", stream)
+    return {k: v[:total] for k, v in bufs.items()}
+
+
+def ai_channels(bank: Bank, layout: torch.Tensor, K_use: Optional[int] = None, plane: int = 0,
+                norm: Optional[Sequence[float]] = None, stream=None) -> torch.Tensor:
+    """Eq. 9's input tensor [batch, n, n, 3] = (Z_t, image of Z_t, dI/dM),
+    optionally mapped to [0, 1] by norm = (lo0, hi0, lo1, hi1, lo2, hi2)."""
+    layout = _mask_batch(layout, bank.n)
+    out = torch.empty((layout.shape[0], bank.n, bank.n, 3), device=layout.device, dtype=torch.float32)
+    nm = None
+    if norm is not None:
+        if len(norm) != 6:
+            raise ValueError("norm needs six values")
+        nm = (C.c_double * 6)(*[float(v) for v in norm])
+    _check(_lib.litho_ai_channels(bank.handle, _dev_ptr(layout, "layout"), layout.shape[0],
+                                  bank.K if K_use is None else int(K_use), int(plane), nm, _dev_ptr(out, "out"),
+                                  C.c_void_p(_stream_handle(stream))), "litho_ai_channels")
+    return out
+
+
+def image_tiled(bank: Bank, layout: torch.Tensor, halo: int, K_use: Optional[int] = None, prec="fp32",
+                stream=None) -> torch.Tensor:
+    """Image of an [H, W] layout larger than a clip through halo tiling
+    (litho_image_tiled): [n_focus, H, W]."""
+    if layout.dim() != 2:
+        raise ValueError("layout must be [H, W]")
+    H, W = layout.shape
+    out = torch.empty((bank.n_focus, H, W), device=layout.device, dtype=torch.float32)
+    _check(_lib.litho_image_tiled(bank.handle, _dev_ptr(layout, "layout"), H, W, int(halo),
+                                  bank.K if K_use is None else int(K_use), _dev_ptr(out, "image"), prec_code(prec),
+                                  C.c_void_p(_stream_handle(stream))), "litho_image_tiled")
+    return out
+
+
+def image_grad_tiled(bank: Bank, layout: torch.Tensor, target: torch.Tensor, halo: int, slope: float = 50.0,
+                     threshold: float = 0.3, K_use: Optional[int] = None, prec="fp32",
+                     plane_weights: Optional[Sequence[float]] = None, loss: str = "l2", blur_sigma_px: float = 0.0,
+                     want_image: bool = True, stream=None):
+    """Tiled image, loss and layout gradient (litho_image_grad_tiled):
+    (image [n_focus, H, W] or None, loss [1] float64, grad [H, W])."""
+    if layout.dim() != 2 or target.shape != layout.shape:
+        raise ValueError("layout and target must be [H, W]")
+    H, W = layout.shape
+    dev = layout.device
+    img = torch.empty((bank.n_focus, H, W), device=dev, dtype=torch.float32) if want_image else None
+    grad = torch.empty((H, W), device=dev, dtype=torch.float32)
+    lo = torch.empty((1,), device=dev, dtype=torch.float64)
+    pw = None
+    if plane_weights is not None:
+        if len(plane_weights) != bank.n_focus:
+            raise ValueError(f"plane_weights needs {bank.n_focus} values")
+        pw = (C.c_double * bank.n_focus)(*[float(v) for v in plane_weights])
+    resist = A.Resist(slope=slope, threshold=threshold,
+                      plane_weight=None if pw is None else C.cast(pw, C.POINTER(C.c_double)),
+                      blur_sigma_px=float(blur_sigma_px), loss=LOSS_KINDS[loss])
+    _check(_lib.litho_image_grad_tiled(bank.handle, _dev_ptr(layout, "layout"), H, W, int(halo),
+                                       bank.K if K_use is None else int(K_use), _dev_ptr(target, "target"),
+                                       C.byref(resist), _dev_ptr(img, "image"), _dev_ptr(lo, "loss", torch.float64),
+                                       _dev_ptr(grad, "grad"), prec_code(prec), C.c_void_p(_stream_handle(stream))),
+           "litho_image_grad_tiled")
+    return img, lo, grad
 
 
 class LithoImage(torch.autograd.Function):
