@@ -263,6 +263,19 @@ int litho_lowpass(const litho_bank_t *bank, const float *d_in, int count, double
 int litho_contours(int n, const float *d_image, double level, int capacity, int *d_cell, int *d_code,
                    float *d_u, int *d_next, int *d_count, void *hip_stream);
 
+/* litho_contours for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, results and errors, but its count and offset scratch
+ * is a static device array of 2 * 4096 * 64 + 1 ints (about 2 MiB) that each
+ * GPU the library runs on holds until the process ends; nothing is allocated
+ * (no hipMalloc, hipFree or allocating library call).  n above 4096 (the
+ * array's limit) gives LITHO_E_UNSUPPORTED.  Every call on one GPU uses that
+ * GPU's single array: calls that overlap on one GPU (different streams, not
+ * ordered) race and must not be issued; calls ordered on one stream are safe.
+ * Every scratch value a call reads it first writes, so nothing is cleared. */
+int litho_contours_noalloc(int n, const float *d_image, double level, int capacity, int *d_cell, int *d_code,
+                           float *d_u, int *d_next, int *d_count, void *hip_stream);
+
 /* Eq. 6's target level and Eq. 8's through-focus rule. */
 typedef struct litho_epe_rule {
   double t_eff;     /* E_tgt on the target edge (the printing threshold) */

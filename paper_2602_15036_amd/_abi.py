@@ -103,6 +103,7 @@ SIGNATURES = {
                                    C.c_int, VP]),
     "litho_lowpass": (C.c_int, [VP, VP, C.c_int, C.c_double, C.c_double, VP, VP]),
     "litho_contours": (C.c_int, [C.c_int, VP, C.c_double, C.c_int, VP, VP, VP, VP, VP, VP]),
+    "litho_contours_noalloc": (C.c_int, [C.c_int, VP, C.c_double, C.c_int, VP, VP, VP, VP, VP, VP]),
     "litho_epe": (C.c_int, [C.c_int, VP, VP, C.c_int, C.POINTER(EpeRule), C.c_int, VP, VP, VP, VP, VP]),
     "litho_ai_channels": (C.c_int, [VP, VP, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), VP, VP]),
     "litho_image_tiled": (C.c_int, [VP, VP, C.c_int, C.c_int, C.c_int, C.c_int, VP, C.c_int, VP]),

@@ -13,6 +13,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "common.hpp"
 #include "post.hpp"
@@ -446,6 +447,15 @@ __global__ __launch_bounds__(256) void k_fill(float *__restrict__ a, size_t n, f
 
 }  // namespace dev
 
+// ---------------------------------------------------------------- allocation-free scratch
+// Counts and offsets of the compaction passes for the largest supported
+// image (n = 4096: 4096 rows x 64 chunks, twice, plus the total), for the
+// allocation-free contour entry point.  Every device that runs it holds one
+// copy for the life of the process.
+constexpr int kNoAllocMaxN = 4096;
+constexpr size_t kNoAllocInts = 2 * size_t(kNoAllocMaxN) * ((kNoAllocMaxN + 63) / 64) + 1;
+static __device__ __align__(256) int scratch[kNoAllocInts];
+
 // ======================================================================== host launchers
 
 namespace {
@@ -461,6 +471,72 @@ unsigned wave_blocks(int items) { return unsigned((items + 3) / 4); }
 }  // namespace
 
 int compaction_chunks(int n) { return (n + 63) / 64; }
+
+int noalloc_max_n() { return kNoAllocMaxN; }
+
+// Device address of this device's copy of the static scratch array, looked up
+// once per device (the array's name in host code is only a stand-in).
+int noalloc_scratch(int **out, size_t *ints) {
+  static std::mutex mu;
+  static int *addr[64] = {};
+  int d = 0;
+  LITHO_HIP_TRY(hipGetDevice(&d));
+  if (d < 0 || d >= 64) {
+    set_error("litho: device %d beyond the 64 the allocation-free scratch table covers", d);
+    return LITHO_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[d]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("litho: hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+      return LITHO_E_HIP;
+    }
+    addr[d] = static_cast<int *>(p);
+  }
+  *out = addr[d];
+  *ints = kNoAllocInts;
+  return LITHO_OK;
+}
+
+int run_contours(const float *img, int n, float level, int *cnt, int *off, int *total, int cap, int *cell,
+                 int *code, float *u, int *next, hipStream_t s) {
+  const int nch = compaction_chunks(n), items = n * nch;
+  dev::Img im{img, n};
+  prof_begin("contour_count", s);
+  hipLaunchKernelGGL(dev::k_contour_count, dim3(wave_blocks(items)), dim3(256), 0, s, im, level, nch, cnt);
+  prof_end("contour_count", s);
+  LITHO_TRY(check_launch("contour_count"));
+  prof_begin("scan_counts", s);
+  hipLaunchKernelGGL(dev::k_scan_counts, dim3(1), dim3(1024), 0, s, cnt, items, off, total);
+  prof_end("scan_counts", s);
+  LITHO_TRY(check_launch("scan_counts"));
+  prof_begin("contour_emit", s);
+  hipLaunchKernelGGL(dev::k_contour_emit, dim3(wave_blocks(items)), dim3(256), 0, s, im, level, nch, off, cap, cell,
+                     code, u, next);
+  prof_end("contour_emit", s);
+  return check_launch("contour_emit");
+}
+
+int run_epe(const float *target, const float *E, int n, int P, const EpeRule &rule, int *cnt, int *off,
+            int *total, int cap, int *site, int *dir, float *epe, hipStream_t s) {
+  const int nch = compaction_chunks(n), items = n * nch;
+  dev::Img tg{target, n};
+  prof_begin("site_count", s);
+  hipLaunchKernelGGL(dev::k_site_count, dim3(wave_blocks(items)), dim3(256), 0, s, tg, nch, cnt);
+  prof_end("site_count", s);
+  LITHO_TRY(check_launch("site_count"));
+  prof_begin("scan_counts", s);
+  hipLaunchKernelGGL(dev::k_scan_counts, dim3(1), dim3(1024), 0, s, cnt, items, off, total);
+  prof_end("scan_counts", s);
+  LITHO_TRY(check_launch("scan_counts"));
+  prof_begin("site_emit", s);
+  hipLaunchKernelGGL(dev::k_site_emit, dim3(wave_blocks(items)), dim3(256), 0, s, tg, E, P, nch, off, cap, rule,
+                     site, dir, epe);
+  prof_end("site_emit", s);
+  return check_launch("site_emit");
+}
 
 int run_tile_gather(const float *layout, const TileGeo &g, int cnt, float *out, hipStream_t s) {
   const size_t nn = size_t(g.n) * g.n;

@@ -48,6 +48,11 @@ int run_fill(float *a, size_t n, float v, hipStream_t s);
 // Chunks of 64 columns per row in the compaction passes (contours, EPE sites).
 int compaction_chunks(int n);
 
+// Largest image side of the allocation-free contour entry point, and this
+// device's address (and size in ints) of the static scratch it uses.
+int noalloc_max_n();
+int noalloc_scratch(int **out, size_t *ints);
+
 // Marching squares of one n x n image at `level`.  cnt: [n * chunks] scratch,
 // off: [n * chunks + 1] scratch, total: device int receiving the segment count.
 // Segments with index >= cap are not written.

@@ -165,6 +165,31 @@ extern "C" int litho_contours(int n, const float *d_image, double level, int cap
   return run_contours(d_image, n, float(level), scr, scr + m, d_count, capacity, d_cell, d_code, d_u, d_next, s);
 }
 
+extern "C" int litho_contours_noalloc(int n, const float *d_image, double level, int capacity, int *d_cell,
+                                      int *d_code, float *d_u, int *d_next, int *d_count, void *hip_stream) {
+  clear_error();
+  if (n < 2 || n > noalloc_max_n()) {
+    set_error("litho_contours_noalloc: n=%d outside 2..%d (the static scratch is sized for %d)", n, noalloc_max_n(),
+              noalloc_max_n());
+    return LITHO_E_UNSUPPORTED;
+  }
+  if (!d_image || !d_count || capacity < 0 || (capacity > 0 && (!d_cell || !d_code || !d_u || !d_next))) {
+    set_error("litho_contours_noalloc: NULL image or count, negative capacity, or NULL outputs with capacity > 0");
+    return LITHO_E_INVALID;
+  }
+  int *scr = nullptr;
+  size_t ints = 0;
+  LITHO_TRY(noalloc_scratch(&scr, &ints));
+  const size_t m = size_t(n) * compaction_chunks(n);
+  if (2 * m + 1 > ints) {
+    set_error("litho_contours_noalloc: %zu scratch ints needed, %zu available", 2 * m + 1, ints);
+    return LITHO_E_UNSUPPORTED;
+  }
+  // every count and offset the passes read is written by them first: nothing to clear
+  return run_contours(d_image, n, float(level), scr, scr + m, d_count, capacity, d_cell, d_code, d_u, d_next,
+                      static_cast<hipStream_t>(hip_stream));
+}
+
 extern "C" int litho_epe(int n, const float *d_target, const float *d_latent, int n_planes,
                          const litho_epe_rule_t *rule, int capacity, int *d_site, int *d_dir, float *d_epe,
                          int *d_count, void *hip_stream) {
