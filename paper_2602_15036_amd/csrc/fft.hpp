@@ -309,6 +309,35 @@ __device__ __forceinline__ int lpad(int i) { return i + M * (i >> 5); }
 template <int L>
 constexpr int lds_len() { return L + pad_max(typename PadPlan<L>::M{}) * (L / 32) + 4; }
 
+// Half-width exchange: the real parts of a transform cross the LDS first,
+// then the imaginary parts, through one region of four-byte slots, which
+// halves the LDS a transform holds (and so raises the occupancy of the
+// LDS-bound row passes) for twice the LDS instructions.  Only plans whose
+// threads stay inside one wavefront use it.  Row stride (in four-byte slots
+// beyond the padded length) and per-exchange padding come from a bank model
+// of four-byte accesses (64 banks, 32 or 64 lanes a cycle), under which
+// these exchanges are free of conflicts.
+template <int L>
+struct HalfPlan {
+  static constexpr bool ok = false;
+  static constexpr int extra = 0;
+  using M = PadMults<>;
+};
+template <> struct HalfPlan<64> { static constexpr bool ok = true; static constexpr int extra = 5; using M = PadMults<0>; };
+template <> struct HalfPlan<96> { static constexpr bool ok = true; static constexpr int extra = 3; using M = PadMults<0, 0>; };
+template <> struct HalfPlan<128> { static constexpr bool ok = true; static constexpr int extra = 4; using M = PadMults<1>; };
+template <> struct HalfPlan<160> { static constexpr bool ok = true; static constexpr int extra = 3; using M = PadMults<0, 0>; };
+template <> struct HalfPlan<192> { static constexpr bool ok = true; static constexpr int extra = 24; using M = PadMults<1, 4>; };
+template <> struct HalfPlan<256> { static constexpr bool ok = true; static constexpr int extra = 8; using M = PadMults<1>; };
+template <> struct HalfPlan<320> { static constexpr bool ok = true; static constexpr int extra = 8; using M = PadMults<1, 4>; };
+template <> struct HalfPlan<384> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 4>; };
+template <> struct HalfPlan<512> { static constexpr bool ok = true; static constexpr int extra = 32; using M = PadMults<1, 4>; };
+template <> struct HalfPlan<640> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 4, 8>; };
+template <> struct HalfPlan<768> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 4>; };
+// four-byte slots of one transform's region
+template <int L>
+constexpr int lds_len_half() { return L + pad_max(typename HalfPlan<L>::M{}) * (L / 32) + HalfPlan<L>::extra; }
+
 // Twiddle table layout.  Pass p (radix R after radices multiplying to S > 1)
 // owns S * (R - 1) consecutive entries starting at tw_offset<p>; entry
 // [k][r - 1] = exp(-2 pi i k r / (S R)).  A butterfly therefore reads its
@@ -404,6 +433,73 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ b
   }
 }
 
+// The same pass with the half-width exchange (see HalfPlan): butterflies in
+// place, then the real parts and the imaginary parts cross the LDS in turn.
+template <int L, int T, int DIR, int R, int S, int OFF, bool LAST, int M>
+__device__ __forceinline__ void stockham_pass_half(cf (&v)[L / T], float *__restrict__ buf, int t,
+                                                   const cf *__restrict__ tw) {
+  constexpr int E = L / T;
+  constexpr int NB = E / R;
+  static_assert(E % R == 0, "radix must divide the per-thread count");
+  static_assert(T <= 64, "the half-width exchange orders its two halves within one wavefront");
+  const cf *twp = opaque(tw);
+#pragma unroll
+  for (int mb = 0; mb < NB; ++mb) {
+    const int j = t + T * mb;
+    cf u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = v[mb + r * NB];
+    if constexpr (S > 1) {
+      const cf *tb = twp + OFF + (j % S) * (R - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cf w = tb[r - 1];
+        if constexpr (DIR > 0) w.y = -w.y;
+        u[r] = cmul(u[r], w);
+      }
+    }
+    Dft<R, DIR>::run(u);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[mb + r * NB] = u[r];
+  }
+  if constexpr (!LAST) {
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb) {
+      const int j = t + T * mb, base = (j / S) * S * R + (j % S);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lpad<M>(base + r * S)] = v[mb + r * NB].x;
+    }
+    xsync<T>();
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i].x = buf[lpad<M>(t + T * i)];
+    xsync<T>();
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb) {
+      const int j = t + T * mb, base = (j / S) * S * R + (j % S);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lpad<M>(base + r * S)] = v[mb + r * NB].y;
+    }
+    xsync<T>();
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i].y = buf[lpad<M>(t + T * i)];
+    xsync<T>();
+  }
+}
+
+template <int L, int T, int DIR, int S, int OFF, int P, int R, int... Rest>
+__device__ __forceinline__ void run_passes_half(cf (&v)[L / T], float *buf, int t, const cf *tw) {
+  stockham_pass_half<L, T, DIR, R, S, OFF, sizeof...(Rest) == 0, PadAt<P, typename HalfPlan<L>::M>::value>(
+      v, buf, t, tw);
+  if constexpr (sizeof...(Rest) > 0)
+    run_passes_half<L, T, DIR, S * R, OFF + (S > 1 ? S * (R - 1) : 0), P + 1, Rest...>(v, buf, t, tw);
+}
+
+template <int L, int DIR, int... Rs>
+__device__ __forceinline__ void fft_half_impl(cf (&v)[L / FftPlan<L>::T], float *buf, int t, const cf *tw,
+                                              Radices<Rs...>) {
+  run_passes_half<L, FftPlan<L>::T, DIR, 1, 0, 0, Rs...>(v, buf, t, tw);
+}
+
 template <int L, int T, int DIR, int S, int OFF, int P, int R, int... Rest>
 __device__ __forceinline__ void run_passes(cf (&v)[L / T], cf *buf, int t, const cf *tw) {
   stockham_pass<L, T, DIR, R, S, OFF, sizeof...(Rest) == 0, PadAt<P, typename PadPlan<L>::M>::value>(v, buf, t,
@@ -457,6 +553,13 @@ __device__ __forceinline__ void fft(cf (&v)[L / FftPlan<L>::T], cf *buf, int t, 
   // the mask restores the known range 0 <= t < T after the opaque copy, so
   // padded LDS addresses of t + T*i fold into immediate offsets
   fft_impl<L, DIR>(v, buf, opaque_lane(t) & (FftPlan<L>::T - 1), tw, typename FftPlan<L>::R{});
+}
+
+// Same transform with the half-width exchange; buf: lds_len_half<L>() floats.
+template <int L, int DIR>
+__device__ __forceinline__ void fft_half(cf (&v)[L / FftPlan<L>::T], float *buf, int t, const cf *tw) {
+  static_assert(HalfPlan<L>::ok, "no half-width exchange plan for this length");
+  fft_half_impl<L, DIR>(v, buf, opaque_lane(t) & (FftPlan<L>::T - 1), tw, typename FftPlan<L>::R{});
 }
 
 }  // namespace dev

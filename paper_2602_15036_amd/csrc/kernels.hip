@@ -580,12 +580,28 @@ template <int Q, bool PR>
 struct AdjRowWaves {
   static constexpr int value = (PR && FftPlan<Q>::T > 32 && RowWaves<Q>::value > 3) ? 3 : RowWaves<Q>::value;
 };
+// Exchange region of one row of the k-loop row passes, in four-byte slots:
+// the half-width exchange where the plan has one (half the LDS per row, so
+// twice the resident rows), else complex slots.
+template <int Q>
+struct RowXch {
+  static constexpr bool half = HalfPlan<Q>::ok;
+  static constexpr int floats = half ? lds_len_half<Q>() : 2 * lds_len<Q>();
+};
+template <int Q, int DIR>
+__device__ __forceinline__ void row_fft(cf (&v)[Q / FftPlan<Q>::T], float *xch, int t, const cf *tw) {
+  if constexpr (RowXch<Q>::half)
+    fft_half<Q, DIR>(v, xch, t, tw);
+  else
+    fft<Q, DIR>(v, reinterpret_cast<cf *>(xch), t, tw);
+}
+
 // Waves per SIMD that the LDS of a 256-thread row-pass block (exchange rows
 // and staged twiddles) allows on a 160 KB CU; a register target above it buys
 // nothing and only constrains the schedule.
 template <int Q>
 struct RowLdsWaves {
-  static constexpr size_t bytes = size_t(256 / FftPlan<Q>::T) * lds_len<Q>() * sizeof(cf) + TwLds<Q>::bytes;
+  static constexpr size_t bytes = size_t(256 / FftPlan<Q>::T) * RowXch<Q>::floats * sizeof(float) + TwLds<Q>::bytes;
   static constexpr int value = int(163840 / bytes) < 1 ? 1 : int(163840 / bytes);
 };
 template <int W, int Q>
@@ -604,8 +620,9 @@ __global__ __launch_bounds__(256, (CapWaves<RowWaves<Q>::value, Q>::value)) void
   extern __shared__ cf smem[];
   const int row = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * RPB + row, clip = blockIdx.y;
-  cf *xch = smem + row * lds_len<Q>();
-  const cf *tw = stage_twiddles<Q>(tw_table, smem + RPB * lds_len<Q>());
+  float *const xbase = reinterpret_cast<float *>(smem);
+  float *xch = xbase + row * RowXch<Q>::floats;
+  const cf *tw = stage_twiddles<Q>(tw_table, reinterpret_cast<cf *>(xbase + RPB * RowXch<Q>::floats));
   float acc[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) acc[i] = 0.f;
@@ -625,7 +642,7 @@ __global__ __launch_bounds__(256, (CapWaves<RowWaves<Q>::value, Q>::value)) void
     } else {
       io.load(v, yc + k * kstride);
     }
-    fft<Q, +1>(v, xch, t, tw);
+    row_fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) acc[i] += cabs2(v[i]);
   }
@@ -643,7 +660,7 @@ __global__ __launch_bounds__(256, (CapWaves<RowWaves<Q>::value, Q>::value)) void
     cf v[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = cmake(acc[i], 0.f);
-    fft<Q, -1>(v, xch, t, tw);
+    row_fft<Q, -1>(v, xch, t, tw);
     store_band_row_v<Q, T>(v, Ib + size_t(clip) * g.ntD * size_t(Q) * kC, unsigned(size_t(g.Dp) * Q * sizeof(cf)),
                            y, t, 2 * g.b, g.Dp, g.dose / (float(Q) * float(Q)));
   }
@@ -663,8 +680,9 @@ __global__ __launch_bounds__(256, (CapWaves<AdjRowWaves<Q, PR>::value, Q>::value
   extern __shared__ cf smem[];
   const int row = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * RPB + row, clip = blockIdx.y;
-  cf *xch = smem + row * lds_len<Q>();
-  const cf *tw = stage_twiddles<Q>(tw_table, smem + RPB * lds_len<Q>());
+  float *const xbase = reinterpret_cast<float *>(smem);
+  float *xch = xbase + row * RowXch<Q>::floats;
+  const cf *tw = stage_twiddles<Q>(tw_table, reinterpret_cast<cf *>(xbase + RPB * RowXch<Q>::floats));
   float gr[E];
   if constexpr (GIN == 0) {
     const float *gsrc = Greal + clip * g_clip_stride + size_t(y) * Q;
@@ -674,7 +692,7 @@ __global__ __launch_bounds__(256, (CapWaves<AdjRowWaves<Q, PR>::value, Q>::value
     cf v[E];
     load_band_row_v<Q, T>(v, Gband + size_t(clip) * g.ntD * size_t(Q) * kC, unsigned(size_t(g.Dp) * Q * sizeof(cf)),
                           y, t, 2 * g.b);
-    fft<Q, +1>(v, xch, t, tw);
+    row_fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) gr[i] = v[i].x * g.dose;
   }
@@ -695,10 +713,10 @@ __global__ __launch_bounds__(256, (CapWaves<AdjRowWaves<Q, PR>::value, Q>::value
     } else {
       io.load(v, yc + k * kstride);
     }
-    fft<Q, +1>(v, xch, t, tw);
+    row_fft<Q, +1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = cscale(v[i], gr[i]);
-    fft<Q, -1>(v, xch, t, tw);
+    row_fft<Q, -1>(v, xch, t, tw);
     io.store(v, yc + k * kstride, g.Bp, 1.0f);
   }
 }
@@ -1369,7 +1387,7 @@ int pass_x_fwd_q(const cf *Y, const EpiPtrs &ep, cf *Ib, const PassGeo &pg, cons
   Geo g = to_geo(pg);
   Epi e = to_epi(ep);
   const bool band = Ib != nullptr;
-  size_t sh = size_t(RPB) * lds_len<Q>() * sizeof(cf);
+  size_t sh = size_t(RPB) * dev::RowXch<Q>::floats * sizeof(float);
   sh = std::max(sh, size_t(256) * sizeof(double)) + dev::TwLds<Q>::bytes;
   const bool pr = dev::prunable<Q>(g.b);
   const dim3 grid(Q / RPB, nclips);
@@ -1392,7 +1410,7 @@ int pass_x_adj_q(cf *Y, const float *G, size_t g_clip_stride, const cf *Gband, c
   constexpr int T = FftPlan<Q>::T, RPB = 256 / T;
   Geo g = to_geo(pg);
   const bool band = Gband != nullptr;
-  const size_t sh = size_t(RPB) * lds_len<Q>() * sizeof(cf) + dev::TwLds<Q>::bytes;
+  const size_t sh = size_t(RPB) * dev::RowXch<Q>::floats * sizeof(float) + dev::TwLds<Q>::bytes;
   const bool pr = dev::prunable<Q>(g.b);
   const dim3 grid(Q / RPB, nclips);
 #define LITHO_PX_ADJ(GIN, PR)                                                                              \
