@@ -355,6 +355,10 @@ int litho_profile_enable(int on);
 int litho_profile_read(char *buf, size_t cap);
 
 /* ---------------------------------------------------------------- serving
+ * Image formation and forward/adjoint modelling served as a stream of
+ * batched work that keeps the device busy (Sec. V, inspection pipelines),
+ * with data kept on the device and unavoidable host transfers staged in
+ * pinned memory (Sec. II-D).
  * A persistent request loop (continuous batching): requests of mixed clip
  * size arrive at any time, are admitted while their device footprint fits in
  * hbm_budget bytes and a slot is free, run on that slot's own stream
@@ -363,7 +367,10 @@ int litho_profile_read(char *buf, size_t cap);
 typedef struct litho_server litho_server_t;
 
 typedef struct litho_serve_cfg {
-  size_t hbm_budget;   /* bytes of device memory requests may hold at once */
+  size_t hbm_budget;   /* bytes of device memory the server may hold: each slot keeps one arena
+                        * (imaging workspace and request I/O buffers) sized for the largest
+                        * request it ran; the sum of arenas and running requests never exceeds
+                        * this, idle arenas are released when a request would not fit */
   int max_slots;       /* concurrent requests on the device (streams), 1..64 */
   int max_queue;       /* pending requests before submit returns LITHO_E_BUSY */
 } litho_serve_cfg_t;
@@ -406,8 +413,10 @@ typedef struct litho_result_info {
 int litho_serve_create(litho_bank_t *const *banks, int n_banks, const litho_serve_cfg_t *cfg,
                        litho_server_t **out);
 
-/* Queue a request; *ticket receives its id.  Host masks/targets are copied,
- * so the caller may reuse them at once (device-resident requests: see
+/* Queue a request; *ticket receives its id.  Host masks/targets are copied
+ * on the calling thread (into pinned staging from a server-wide pool capped by
+ * LITHO_SERVE_PINNED_MB, default 4096, else into pageable memory), so the
+ * caller may reuse them at once (device-resident requests: see
  * litho_request_t).  LITHO_E_NOMEM if the request can never fit hbm_budget,
  * LITHO_E_BUSY if the queue is full, LITHO_E_INVALID for a malformed request. */
 int litho_serve_submit(litho_server_t *srv, const litho_request_t *req, uint64_t *ticket);
@@ -415,7 +424,7 @@ int litho_serve_submit(litho_server_t *srv, const litho_request_t *req, uint64_t
 /* Wait up to timeout_us (0 = do not wait, < 0 = forever) for a ticket.
  * Returns LITHO_PENDING while running; on completion copies the image
  * ([n_focus][n][n]) and, for mode 1, the gradient ([n][n]) into the host
- * buffers (either may be NULL; both are ignored for device-resident requests,
+ * buffers on the calling thread (either may be NULL; both are ignored for device-resident requests,
  * whose results are already in their device buffers), fills *info and releases
  * the ticket. */
 int litho_serve_poll(litho_server_t *srv, uint64_t ticket, float *h_image, float *h_grad,

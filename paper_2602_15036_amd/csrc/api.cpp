@@ -616,7 +616,8 @@ namespace litho {
 // so the kernels see dense per-clip arrays.  run_chunk() expects exactly that.
 int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, const float *d_target,
                     const litho_resist_t *resist, const float *d_grad_image, float *d_image, double *d_loss,
-                    float *d_grad_mask, bool grad, int prec, hipStream_t s, int p0, int p1) {
+                    float *d_grad_mask, bool grad, int prec, hipStream_t s, int p0, int p1, char *ext_ws,
+                    size_t ext_bytes) {
   if (batch == 0) return LITHO_OK;
   const bool fused = d_target != nullptr;
   CallOpts o;
@@ -637,7 +638,17 @@ int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, c
   }
   CallLayout L = plan_call(bk, batch, K_use, grad, fused, prec, o.blur_sigma > 0.0);
   char *ws = nullptr;
-  LITHO_TRY(acquire_workspace(bk, s, L.per_clip * size_t(L.chunk), &ws));
+  if (ext_ws) {
+    // the caller's buffer (a serve slot's arena): one clip at a time if needed
+    L.chunk = int(std::max<size_t>(1, std::min<size_t>(size_t(L.chunk), ext_bytes / L.per_clip)));
+    if (ext_bytes < L.per_clip) {
+      set_error("litho: a %zu byte workspace is short of the %zu bytes one clip needs", ext_bytes, L.per_clip);
+      return LITHO_E_INVALID;
+    }
+    ws = ext_ws;
+  } else {
+    LITHO_TRY(acquire_workspace(bk, s, L.per_clip * size_t(L.chunk), &ws));
+  }
   const size_t NN = size_t(bk->host.n) * bk->host.n;
   const int P = bk->host.n_focus;
   for (int c0 = 0; c0 < batch; c0 += L.chunk) {

@@ -70,7 +70,8 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
 int acquire_workspace(litho_bank *bk, hipStream_t s, size_t bytes, char **out);
 int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, const float *d_target,
                     const litho_resist_t *resist, const float *d_grad_image, float *d_image, double *d_loss,
-                    float *d_grad_mask, bool grad, int prec, hipStream_t s, int p0 = 0, int p1 = -1);
+                    float *d_grad_mask, bool grad, int prec, hipStream_t s, int p0 = 0, int p1 = -1,
+                    char *ext_ws = nullptr, size_t ext_bytes = 0);
 int check_prec(int prec, const char *who);
 int acquire_aux(litho_bank *bk, hipStream_t s, size_t bytes, char **out);
 int plane_streams(litho_bank *bk, hipStream_t s, int count, hipStream_t *side, hipEvent_t *ev);

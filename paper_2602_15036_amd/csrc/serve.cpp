@@ -2,19 +2,28 @@
 // litho_serve_* C ABI.
 //
 // Each slot owns a non-blocking HIP stream (default priority), a completion
-// event, device buffers for one request and pinned host staging.  A request
-// on a slot is: pinned copy of its mask (and target) -> H2D -> SOCS image (and
-// loss + gradient) on the slot's stream -> D2H into pinned memory -> event.
-// A device-resident request skips the copies: it reads and writes the
-// caller's device buffers directly.
+// event and one device arena (request I/O buffers plus the imaging workspace),
+// grown to the largest request the slot has run; the scheduler counts every
+// arena against the HBM budget and releases idle ones when a request would
+// not fit otherwise.  Host requests are staged in pinned buffers from a
+// server-wide pool: the submitting thread copies the mask (and target) in,
+// the slot's stream moves them to the arena and the results back into pinned
+// memory, and the polling thread copies them out, so the scheduler thread
+// does no bulk host copy.  When the pool reaches its cap
+// (LITHO_SERVE_PINNED_MB, default 4096) a request falls back to pageable
+// copies through the slot's own staging.  A device-resident request reads and
+// writes the caller's device buffers directly.
 // Slots run concurrently, so requests of different clip sizes and banks
 // overlap on the device; every request keeps the bank's resident kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -24,10 +33,65 @@
 namespace litho {
 namespace {
 
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Pinned host buffers, reused across requests (power-of-two size classes).
+class PinnedPool {
+ public:
+  explicit PinnedPool(size_t cap) : cap_(cap) {}
+  ~PinnedPool() {
+    for (auto &kv : free_) (void)hipHostFree(kv.second);
+  }
+  // nullptr when the cap would be exceeded or the allocation fails
+  void *get(size_t bytes, size_t *cls) {
+    size_t c = 4096;
+    while (c < bytes) c <<= 1;
+    *cls = c;
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = free_.find(c);
+    if (it != free_.end()) {
+      void *p = it->second;
+      free_.erase(it);
+      return p;
+    }
+    if (total_ + c > cap_) return nullptr;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    total_ += c;
+    return p;
+  }
+  void put(void *p, size_t cls) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.emplace(cls, p);
+  }
+
+ private:
+  std::mutex mu_;
+  std::multimap<size_t, void *> free_;
+  size_t total_ = 0, cap_;
+};
+
+size_t pinned_cap() {
+  const char *e = std::getenv("LITHO_SERVE_PINNED_MB");
+  size_t mb = 4096;
+  if (e && *e) mb = size_t(std::strtoull(e, nullptr, 10));
+  return mb << 20;
+}
+
 struct ServeReq {
   litho_bank *bank = nullptr;
   int K_use = 0, mode = 0, n = 0, P = 1, prec = LITHO_PREC_FP32;
   double slope = 0, thr = 0;
+  size_t ws_bytes = 0;       // imaging workspace of one clip
+  // host I/O through pinned staging (in: mask, target; out: image, grad, loss)
+  PinnedPool *pool = nullptr;
+  float *p_in = nullptr, *p_out = nullptr;
+  size_t in_cls = 0, out_cls = 0;
+  // host I/O fallback (pool at its cap): pageable copies
   std::vector<float> mask, target;
   std::vector<float> image, grad;
   double loss = 0;
@@ -36,6 +100,15 @@ struct ServeReq {
   float *d_image = nullptr, *d_grad = nullptr;
   double *d_loss = nullptr;
   bool on_device() const { return d_mask != nullptr; }
+  size_t px() const { return size_t(n) * n; }
+  // pinned output: image [P][px], grad [px], loss (double, 8-byte aligned)
+  size_t out_loss_offset() const { return (px() * (P + 1) + 1) & ~size_t(1); }
+  ~ServeReq() {
+    if (pool) {
+      pool->put(p_in, in_cls);
+      pool->put(p_out, out_cls);
+    }
+  }
 };
 
 class HipExecutor final : public serve::Executor {
@@ -43,10 +116,10 @@ class HipExecutor final : public serve::Executor {
   struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    size_t dev_px = 0, host_px = 0;  // capacity in pixels (per plane for image)
-    int dev_planes = 0, host_planes = 0;
-    float *d_mask = nullptr, *d_target = nullptr, *d_image = nullptr, *d_grad = nullptr;
-    double *d_loss = nullptr;
+    char *arena = nullptr;            // device: workspace, then mask, target, image, grad, loss
+    size_t arena_bytes = 0;
+    size_t host_px = 0;               // pageable-fallback staging capacity (pixels, per plane for image)
+    int host_planes = 0;
     float *h_in = nullptr, *h_image = nullptr, *h_grad = nullptr;
     double *h_loss = nullptr;
     std::string error;
@@ -58,7 +131,7 @@ class HipExecutor final : public serve::Executor {
     (void)hipSetDevice(device_);
     for (auto &s : slots_) {
       if (s.stream) (void)hipStreamSynchronize(s.stream);
-      free_dev(s);
+      if (s.arena) (void)hipFree(s.arena);
       free_host(s);
       if (s.done) (void)hipEventDestroy(s.done);
       if (s.stream) (void)hipStreamDestroy(s.stream);
@@ -74,69 +147,76 @@ class HipExecutor final : public serve::Executor {
     return LITHO_OK;
   }
 
+  // Device bytes a request needs on its slot: the imaging workspace of one
+  // clip, plus its I/O buffers unless they are device-resident.
+  static size_t arena_need(size_t ws_bytes, size_t px, int P, bool on_device) {
+    if (on_device) return ws_bytes;
+    return ws_bytes + align_up(2 * px * sizeof(float)) + align_up(px * P * sizeof(float)) +
+           align_up(px * sizeof(float)) + 256;
+  }
+
   int slots() const override { return int(slots_.size()); }
   void thread_init() override { (void)hipSetDevice(device_); }
+  size_t held(int si) const override { return slots_[size_t(si)].arena_bytes; }
+  void trim(int si) override {
+    Slot &s = slots_[size_t(si)];
+    if (!s.arena) return;
+    (void)hipStreamSynchronize(s.stream);
+    (void)hipFree(s.arena);
+    s.arena = nullptr;
+    s.arena_bytes = 0;
+  }
 
   int launch(serve::Job &job, int si) override {
     auto *r = static_cast<ServeReq *>(job.payload.get());
     Slot &s = slots_[size_t(si)];
-    if (r->on_device()) return launch_device(job, *r, s);
-    const size_t px = size_t(r->n) * r->n;
-    int rc = ensure(s, px, r->P);
+    const size_t px = r->px();
+    int rc = grow(s, job.footprint);
     if (rc != LITHO_OK) {
       job.error = last_error();
       return rc;
     }
-    std::memcpy(s.h_in, r->mask.data(), px * sizeof(float));
-    if (r->mode == 1) std::memcpy(s.h_in + px, r->target.data(), px * sizeof(float));
+    char *ws = s.arena;
+    if (r->on_device()) return run(job, *r, s, ws, r->d_mask, r->d_target, r->d_image, r->d_grad, r->d_loss);
+    char *io = s.arena + r->ws_bytes;
+    float *d_mask = reinterpret_cast<float *>(io);
+    float *d_target = d_mask + px;
+    float *d_image = reinterpret_cast<float *>(io + align_up(2 * px * sizeof(float)));
+    float *d_grad = reinterpret_cast<float *>(reinterpret_cast<char *>(d_image) + align_up(px * r->P * sizeof(float)));
+    double *d_loss = reinterpret_cast<double *>(reinterpret_cast<char *>(d_grad) + align_up(px * sizeof(float)));
     const size_t in_bytes = px * sizeof(float) * (r->mode == 1 ? 2 : 1);
-    if (hipMemcpyAsync(s.d_mask, s.h_in, in_bytes, hipMemcpyHostToDevice, s.stream) != hipSuccess) {
+    const float *src = r->p_in;
+    if (!src) {
+      rc = ensure_host(s, px, r->P);
+      if (rc != LITHO_OK) {
+        job.error = last_error();
+        return rc;
+      }
+      std::memcpy(s.h_in, r->mask.data(), px * sizeof(float));
+      if (r->mode == 1) std::memcpy(s.h_in + px, r->target.data(), px * sizeof(float));
+      src = s.h_in;
+    }
+    if (hipMemcpyAsync(d_mask, src, in_bytes, hipMemcpyHostToDevice, s.stream) != hipSuccess) {
       job.error = "litho_serve: H2D copy failed";
       return LITHO_E_HIP;
     }
-    if (r->mode == 1) {
-      litho_resist_t res{r->slope, r->thr};
-      rc = image_grad_impl(r->bank, s.d_mask, 1, r->K_use, s.d_target, &res, nullptr, s.d_image, s.d_loss,
-                           s.d_grad, true, r->prec, s.stream);
-    } else {
-      rc = image_grad_impl(r->bank, s.d_mask, 1, r->K_use, nullptr, nullptr, nullptr, s.d_image, nullptr, nullptr,
-                           false, r->prec, s.stream);
-    }
+    rc = image_call(*r, s, ws, d_mask, d_target, d_image, d_grad, d_loss);
     if (rc != LITHO_OK) {
       job.error = last_error();
       return rc;
     }
-    bool ok = hipMemcpyAsync(s.h_image, s.d_image, px * r->P * sizeof(float), hipMemcpyDeviceToHost, s.stream) ==
+    float *o_image = r->p_out ? r->p_out : s.h_image;
+    float *o_grad = r->p_out ? r->p_out + px * r->P : s.h_grad;
+    double *o_loss = r->p_out ? reinterpret_cast<double *>(r->p_out + r->out_loss_offset()) : s.h_loss;
+    bool ok = hipMemcpyAsync(o_image, d_image, px * r->P * sizeof(float), hipMemcpyDeviceToHost, s.stream) ==
               hipSuccess;
     if (r->mode == 1) {
-      ok = ok && hipMemcpyAsync(s.h_grad, s.d_grad, px * sizeof(float), hipMemcpyDeviceToHost, s.stream) ==
-                     hipSuccess;
-      ok = ok && hipMemcpyAsync(s.h_loss, s.d_loss, sizeof(double), hipMemcpyDeviceToHost, s.stream) == hipSuccess;
+      ok = ok && hipMemcpyAsync(o_grad, d_grad, px * sizeof(float), hipMemcpyDeviceToHost, s.stream) == hipSuccess;
+      ok = ok && hipMemcpyAsync(o_loss, d_loss, sizeof(double), hipMemcpyDeviceToHost, s.stream) == hipSuccess;
     }
     ok = ok && hipEventRecord(s.done, s.stream) == hipSuccess;
     if (!ok) {
       job.error = "litho_serve: D2H copy or event record failed";
-      return LITHO_E_HIP;
-    }
-    return LITHO_OK;
-  }
-
-  int launch_device(serve::Job &job, ServeReq &r, Slot &s) {
-    int rc;
-    if (r.mode == 1) {
-      litho_resist_t res{r.slope, r.thr};
-      rc = image_grad_impl(r.bank, r.d_mask, 1, r.K_use, r.d_target, &res, nullptr, r.d_image, r.d_loss, r.d_grad,
-                           true, r.prec, s.stream);
-    } else {
-      rc = image_grad_impl(r.bank, r.d_mask, 1, r.K_use, nullptr, nullptr, nullptr, r.d_image, nullptr, nullptr,
-                           false, r.prec, s.stream);
-    }
-    if (rc != LITHO_OK) {
-      job.error = last_error();
-      return rc;
-    }
-    if (hipEventRecord(s.done, s.stream) != hipSuccess) {
-      job.error = "litho_serve: event record failed";
       return LITHO_E_HIP;
     }
     return LITHO_OK;
@@ -161,7 +241,12 @@ class HipExecutor final : public serve::Executor {
       r->loss = std::numeric_limits<double>::quiet_NaN();
       return LITHO_OK;
     }
-    const size_t px = size_t(r->n) * r->n;
+    if (r->p_out) {
+      // results wait in the request's pinned buffer for the polling thread
+      if (r->mode == 1) r->loss = *reinterpret_cast<const double *>(r->p_out + r->out_loss_offset());
+      return LITHO_OK;
+    }
+    const size_t px = r->px();
     r->image.assign(s.h_image, s.h_image + px * r->P);
     if (r->mode == 1) {
       r->grad.assign(s.h_grad, s.h_grad + px);
@@ -171,15 +256,51 @@ class HipExecutor final : public serve::Executor {
   }
 
  private:
-  static void free_dev(Slot &s) {
-    for (float *p : {s.d_mask, s.d_image, s.d_grad})
-      if (p) (void)hipFree(p);
-    if (s.d_loss) (void)hipFree(s.d_loss);
-    s.d_mask = s.d_target = s.d_image = s.d_grad = nullptr;
-    s.d_loss = nullptr;
-    s.dev_px = 0;
-    s.dev_planes = 0;
+  int run(serve::Job &job, ServeReq &r, Slot &s, char *ws, const float *d_mask, const float *d_target,
+          float *d_image, float *d_grad, double *d_loss) {
+    int rc = image_call(r, s, ws, d_mask, d_target, d_image, d_grad, d_loss);
+    if (rc != LITHO_OK) {
+      job.error = last_error();
+      return rc;
+    }
+    if (hipEventRecord(s.done, s.stream) != hipSuccess) {
+      job.error = "litho_serve: event record failed";
+      return LITHO_E_HIP;
+    }
+    return LITHO_OK;
   }
+
+  static int image_call(ServeReq &r, Slot &s, char *ws, const float *d_mask, const float *d_target,
+                        float *d_image, float *d_grad, double *d_loss) {
+    if (r.mode == 1) {
+      litho_resist_t res{r.slope, r.thr};
+      return image_grad_impl(r.bank, d_mask, 1, r.K_use, d_target, &res, nullptr, d_image, d_loss, d_grad, true,
+                             r.prec, s.stream, 0, -1, ws, r.ws_bytes);
+    }
+    return image_grad_impl(r.bank, d_mask, 1, r.K_use, nullptr, nullptr, nullptr, d_image, nullptr, nullptr, false,
+                           r.prec, s.stream, 0, -1, ws, r.ws_bytes);
+  }
+
+  // Grows the slot's arena to `bytes` (scheduler thread, slot idle; the
+  // scheduler has already counted the growth against the budget).
+  int grow(Slot &s, size_t bytes) {
+    if (s.arena_bytes >= bytes) return LITHO_OK;
+    if (s.arena) {
+      (void)hipStreamSynchronize(s.stream);
+      (void)hipFree(s.arena);
+      s.arena = nullptr;
+      s.arena_bytes = 0;
+    }
+    if (hipMalloc(&s.arena, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      s.arena = nullptr;
+      set_error("litho_serve: cannot allocate a %zu byte slot arena", bytes);
+      return LITHO_E_NOMEM;
+    }
+    s.arena_bytes = bytes;
+    return LITHO_OK;
+  }
+
   static void free_host(Slot &s) {
     for (float *p : {s.h_in, s.h_image, s.h_grad})
       if (p) (void)hipHostFree(p);
@@ -190,39 +311,21 @@ class HipExecutor final : public serve::Executor {
     s.host_planes = 0;
   }
 
-  // Grows the slot's buffers to px pixels and P planes (only on the scheduler
-  // thread, while the slot is idle).
-  int ensure(Slot &s, size_t px, int P) {
-    if (s.dev_px < px || s.dev_planes < P) {
-      free_dev(s);
-      const size_t mask_bytes = 2 * px * sizeof(float);  // mask + target, contiguous
-      if (hipMalloc(&s.d_mask, mask_bytes) != hipSuccess || hipMalloc(&s.d_image, px * P * sizeof(float)) !=
-              hipSuccess || hipMalloc(&s.d_grad, px * sizeof(float)) != hipSuccess ||
-          hipMalloc(&s.d_loss, sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        free_dev(s);
-        set_error("litho_serve: cannot allocate slot buffers for %zu pixels", px);
-        return LITHO_E_NOMEM;
-      }
-      s.d_target = s.d_mask + px;
-      s.dev_px = px;
-      s.dev_planes = P;
-    }
-    s.d_target = s.d_mask + px;
-    if (s.host_px < px || s.host_planes < P) {
+  // Pinned staging of the pageable fallback, grown to px pixels and P planes.
+  int ensure_host(Slot &s, size_t px, int P) {
+    if (s.host_px >= px && s.host_planes >= P) return LITHO_OK;
+    free_host(s);
+    if (hipHostMalloc(&s.h_in, 2 * px * sizeof(float), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s.h_image, px * P * sizeof(float), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s.h_grad, px * sizeof(float), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s.h_loss, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
       free_host(s);
-      if (hipHostMalloc(&s.h_in, 2 * px * sizeof(float), hipHostMallocDefault) != hipSuccess ||
-          hipHostMalloc(&s.h_image, px * P * sizeof(float), hipHostMallocDefault) != hipSuccess ||
-          hipHostMalloc(&s.h_grad, px * sizeof(float), hipHostMallocDefault) != hipSuccess ||
-          hipHostMalloc(&s.h_loss, sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        free_host(s);
-        set_error("litho_serve: cannot allocate pinned staging for %zu pixels", px);
-        return LITHO_E_NOMEM;
-      }
-      s.host_px = px;
-      s.host_planes = P;
+      set_error("litho_serve: cannot allocate pinned staging for %zu pixels", px);
+      return LITHO_E_NOMEM;
     }
+    s.host_px = px;
+    s.host_planes = P;
     return LITHO_OK;
   }
 
@@ -235,18 +338,16 @@ class HipExecutor final : public serve::Executor {
 
 struct litho_server {
   std::vector<litho_bank *> banks;
+  std::unique_ptr<litho::PinnedPool> pool;
   std::unique_ptr<litho::HipExecutor> ex;
   std::unique_ptr<litho::serve::Scheduler> sched;
 };
 
 using namespace litho;
 
-// Device bytes a request holds while it runs: the workspace of one clip of
-// its bank, plus the slot's I/O buffers unless its I/O is device-resident.
-static size_t request_footprint(litho_bank *bk, int K_use, int mode, int prec, bool on_device) {
-  const size_t px = size_t(bk->host.n) * bk->host.n;
-  const CallLayout L = plan_call(bk, 1, K_use, mode == 1, mode == 1, prec);
-  return (on_device ? 0 : px * sizeof(float) * (3 + size_t(bk->host.n_focus))) + L.per_clip;
+// Imaging workspace of one clip of a request (its slot arena adds the I/O buffers).
+static size_t request_workspace(litho_bank *bk, int K_use, int mode, int prec) {
+  return plan_call(bk, 1, K_use, mode == 1, mode == 1, prec).per_clip;
 }
 
 extern "C" int litho_serve_create(litho_bank_t *const *banks, int n_banks, const litho_serve_cfg_t *cfg,
@@ -265,6 +366,7 @@ extern "C" int litho_serve_create(litho_bank_t *const *banks, int n_banks, const
     }
   auto srv = std::make_unique<litho_server>();
   srv->banks.assign(banks, banks + n_banks);
+  srv->pool = std::make_unique<PinnedPool>(pinned_cap());
   srv->ex = std::make_unique<HipExecutor>(cfg->max_slots, banks[0]->device);
   LITHO_TRY(srv->ex->init());
   srv->sched = std::make_unique<serve::Scheduler>(srv->ex.get(), cfg->hbm_budget, cfg->max_queue);
@@ -304,6 +406,7 @@ extern "C" int litho_serve_submit(litho_server_t *srv, const litho_request_t *re
   r->slope = req->slope;
   r->thr = req->threshold;
   const size_t px = size_t(r->n) * r->n;
+  r->ws_bytes = request_workspace(bk, req->K_use, req->mode, req->prec);
   if (dev) {
     r->d_mask = req->d_mask;
     r->d_target = req->mode == 1 ? req->d_target : nullptr;
@@ -311,11 +414,25 @@ extern "C" int litho_serve_submit(litho_server_t *srv, const litho_request_t *re
     r->d_grad = req->mode == 1 ? req->d_grad : nullptr;
     r->d_loss = req->mode == 1 ? req->d_loss : nullptr;
   } else {
-    r->mask.assign(req->h_mask, req->h_mask + px);
-    if (req->mode == 1) r->target.assign(req->h_target, req->h_target + px);
+    // copy the inputs on this (the caller's) thread, into pinned staging when
+    // the pool has room, else into pageable memory
+    r->pool = srv->pool.get();
+    const size_t in_bytes = px * sizeof(float) * (req->mode == 1 ? 2 : 1);
+    const size_t out_bytes = (px * size_t(r->P + 1) + 4) * sizeof(float);
+    r->p_in = static_cast<float *>(r->pool->get(in_bytes, &r->in_cls));
+    r->p_out = r->p_in ? static_cast<float *>(r->pool->get(out_bytes, &r->out_cls)) : nullptr;
+    if (r->p_in && r->p_out) {
+      std::memcpy(r->p_in, req->h_mask, px * sizeof(float));
+      if (req->mode == 1) std::memcpy(r->p_in + px, req->h_target, px * sizeof(float));
+    } else {
+      r->pool->put(r->p_in, r->in_cls);
+      r->p_in = nullptr;
+      r->mask.assign(req->h_mask, req->h_mask + px);
+      if (req->mode == 1) r->target.assign(req->h_target, req->h_target + px);
+    }
   }
   auto job = std::make_shared<serve::Job>();
-  job->footprint = request_footprint(bk, req->K_use, req->mode, req->prec, dev);
+  job->footprint = HipExecutor::arena_need(r->ws_bytes, px, r->P, dev);
   job->payload = r;
   const int rc = srv->sched->submit(job, ticket);
   if (rc == LITHO_E_NOMEM)
@@ -356,6 +473,14 @@ extern "C" int litho_serve_poll(litho_server_t *srv, uint64_t ticket, float *h_i
     return job->status;
   }
   if (r->on_device()) return LITHO_OK;
+  const size_t px = r->px();
+  if (r->p_out) {
+    // out of the request's pinned buffer on this (the polling) thread; the
+    // buffers go back to the pool with the request
+    if (h_image) std::memcpy(h_image, r->p_out, px * r->P * sizeof(float));
+    if (h_grad && r->mode == 1) std::memcpy(h_grad, r->p_out + px * r->P, px * sizeof(float));
+    return LITHO_OK;
+  }
   if (h_image) std::memcpy(h_image, r->image.data(), r->image.size() * sizeof(float));
   if (h_grad && r->mode == 1) std::memcpy(h_grad, r->grad.data(), r->grad.size() * sizeof(float));
   return LITHO_OK;

@@ -71,6 +71,11 @@ class Executor {
   virtual int collect(Job &job, int slot) = 0;
   // Called once on the scheduler thread before anything else.
   virtual void thread_init() {}
+  // Device bytes the slot keeps between requests (buffers sized for the
+  // largest request it has run), and their release while the slot is idle.
+  // Admission counts these against the budget.
+  virtual size_t held(int /*slot*/) const { return 0; }
+  virtual void trim(int /*slot*/) {}
 };
 
 class Scheduler {
@@ -167,24 +172,58 @@ class Scheduler {
       }
       for (auto &a : active)
         if (ex_->ready(a.first)) finish(a.second, a.first, ex_->collect(*a.second, a.first));
-      // 2. admission, strict FIFO
+      // 2. admission, strict FIFO.  A slot commits max(kept bytes, footprint
+      // of its running request); the head request is admitted on a free slot
+      // when the total commitment stays within the budget, releasing the kept
+      // buffers of other idle slots (largest first) if that makes it fit.
       for (;;) {
         std::shared_ptr<Job> job;
         int slot = -1;
         {
           std::lock_guard<std::mutex> lk(mu_);
           if (queue_.empty()) break;
-          for (size_t s = 0; s < running_.size(); ++s)
-            if (!running_[s]) {
+          const size_t need = queue_.front()->footprint;
+          // free slot: one already holding enough, else the one holding most
+          for (size_t s = 0; s < running_.size(); ++s) {
+            if (running_[s]) continue;
+            const size_t h = ex_->held(int(s));
+            if (slot < 0) {
               slot = int(s);
-              break;
+              continue;
             }
-          if (slot < 0 || in_use_ + queue_.front()->footprint > budget_) break;
+            const size_t hb = ex_->held(slot);
+            if ((h >= need && (hb < need || h < hb)) || (hb < need && h > hb)) slot = int(s);
+          }
+          if (slot < 0) break;
+          auto committed = [&] {
+            size_t c = 0;
+            for (size_t s = 0; s < running_.size(); ++s) {
+              const size_t h = ex_->held(int(s));
+              const size_t f = running_[s] ? running_[s]->footprint : 0;
+              c += h > f ? h : f;
+            }
+            return c;
+          };
+          auto with_job = [&] {
+            const size_t h = ex_->held(slot);
+            return committed() - h + (h > need ? h : need);
+          };
+          while (with_job() > budget_) {
+            int victim = -1;
+            for (size_t s = 0; s < running_.size(); ++s)
+              if (!running_[s] && int(s) != slot && ex_->held(int(s)) > 0 &&
+                  (victim < 0 || ex_->held(int(s)) > ex_->held(victim)))
+                victim = int(s);
+            if (victim < 0) break;
+            ex_->trim(victim);
+          }
+          if (with_job() > budget_) break;
           job = queue_.front();
           queue_.pop_front();
           running_[size_t(slot)] = job;
           in_use_ += job->footprint;
-          if (in_use_ > peak_) peak_ = in_use_;
+          const size_t c = committed();
+          if (c > peak_) peak_ = c;
           job->slot = slot;
           job->state = State::Running;
           job->t_start = now_us();

@@ -65,13 +65,44 @@ class MockExecutor : public Executor {
     r->result = r->value * 2;
     return LITHO_OK;
   }
-  std::mutex mu;
+  mutable std::mutex mu;
   std::vector<uint64_t> starts;
   size_t max_concurrent = 0;
 
  private:
   std::vector<double> start_, dur_;
   std::vector<MockReq *> req_;
+};
+
+// An executor whose slots keep buffers sized for the largest request they
+// ran (like device arenas) until the scheduler trims them.
+class KeepingExecutor : public MockExecutor {
+ public:
+  explicit KeepingExecutor(int n) : MockExecutor(n), kept_(size_t(n), 0) {}
+  int launch(Job &job, int s) override {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (kept_[size_t(s)] < job.footprint) kept_[size_t(s)] = job.footprint;
+      size_t total = 0;
+      for (size_t k : kept_) total += k;
+      max_kept_total = std::max(max_kept_total, total);
+    }
+    return MockExecutor::launch(job, s);
+  }
+  size_t held(int s) const override {
+    std::lock_guard<std::mutex> lk(mu);
+    return kept_[size_t(s)];
+  }
+  void trim(int s) override {
+    std::lock_guard<std::mutex> lk(mu);
+    kept_[size_t(s)] = 0;
+    ++trims;
+  }
+  size_t max_kept_total = 0;
+  int trims = 0;
+
+ private:
+  std::vector<size_t> kept_;
 };
 
 static std::shared_ptr<Job> make_job(size_t fp, double dur, int value, bool fl = false, bool fd = false) {
@@ -174,6 +205,34 @@ int main() {
     }
     for (auto &j : jobs) CHECK(j->state == State::Done && j->status == LITHO_OK);
     std::printf("drain ok\n");
+  }
+  // 5. kept slot buffers count against the budget: their total never exceeds
+  //    it, idle slots are trimmed to admit a request, and everything finishes
+  {
+    KeepingExecutor ex(4);
+    const size_t budget = 100;
+    std::vector<std::shared_ptr<Job>> jobs;
+    {
+      Scheduler sch(&ex, budget, 1000);
+      for (int i = 0; i < 40; ++i) {
+        // runs of small requests fill every slot's buffers, then a large one
+        // needs the buffers of idle slots released
+        const size_t fp = (i % 10 == 9) ? 90 : 20 + size_t(i % 6);
+        auto j = make_job(fp, 100 + (i % 3) * 50, i);
+        uint64_t t;
+        CHECK(sch.submit(j, &t) == LITHO_OK);
+        jobs.push_back(j);
+      }
+      for (auto &j : jobs) {
+        std::shared_ptr<Job> out;
+        CHECK(sch.wait(j->ticket, -1, &out) == LITHO_OK);
+        CHECK(out->status == LITHO_OK);
+      }
+      CHECK(sch.peak_in_use() <= budget);
+    }
+    CHECK(ex.max_kept_total <= budget);
+    CHECK(ex.trims > 0);
+    std::printf("kept buffers ok: max kept %zu of %zu, %d trims\n", ex.max_kept_total, budget, ex.trims);
   }
   std::printf("ALL OK\n");
   return 0;

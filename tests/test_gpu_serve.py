@@ -79,17 +79,23 @@ def test_serve_errors(L, banks):
     with pytest.raises(L.LithoError) as e:
         srv.poll(424242, 256, 1, False, timeout_us=0)
     assert "NOTFOUND" in str(e.value)
+    # a full queue: device-resident submits (no host copy) outpace one slot
+    import torch
+    dm = torch.zeros((512, 512), device="cuda")
+    outs = [torch.empty((1, 512, 512), device="cuda") for _ in range(8)]
+    torch.cuda.synchronize()
     tickets = []
     busy = False
-    for _ in range(8):
+    for i in range(500):
         try:
-            tickets.append(srv.submit(1, np.zeros((512, 512), np.float32), K_use=20))
+            tickets.append(srv.submit_device(1, dm, outs[i % 8], K_use=20))
         except L.LithoError as err:
             assert "BUSY" in str(err)
             busy = True
+            break
     assert busy
     for t in tickets:
-        assert srv.poll(t, 512, 1, False) is not None
+        assert srv.poll_info(t) is not None
     srv.close()
 
 
@@ -131,3 +137,74 @@ def test_device_resident_requests_match_host_requests(L, banks):
         req = L.A.Request(bank=0, K_use=8, mode=0, d_mask=dev_bufs[0]["mask"].data_ptr())
         L._check(L._lib.litho_serve_submit(srv._h, L.C.byref(req), L.C.byref(L.C.c_uint64())), "litho_serve_submit")
     srv.close()
+
+
+def test_large_clips_and_split_modes_alone_equal_mixed(L):
+    # 1024 and 2048 clips, FP32 and split-precision requests in one mix: each
+    # result equals the same request run alone, bit for bit
+    banks = [L.Bank.from_spec(W.serve_optics(n).with_(K=16)) for n in (1024, 2048)]
+    rng = np.random.default_rng(3100)
+    reqs = []
+    for i in range(10):
+        bi = i % 2
+        n = (1024, 2048)[bi]
+        m = W.as_f32_exact(W.curvilinear_mask(n, 500 + i))
+        T = W.manhattan_target(n, 600 + i) if i % 3 else None
+        prec = ("fp32", "f16x3", "bf16")[i % 3]
+        reqs.append((bi, n, m, int(rng.integers(8, 17)), T, prec))
+    srv = L.Server(banks, hbm_budget=24 << 30, max_slots=4)
+    tickets = [srv.submit(bi, m, K_use=K, target=T, prec=p) for (bi, n, m, K, T, p) in reqs]
+    mixed = [srv.poll(t, n, 1, T is not None) for t, (bi, n, m, K, T, p) in zip(tickets, reqs)]
+    spans = sorted((r["t_start_us"], r["t_done_us"]) for r in mixed)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    for (bi, n, m, K, T, p), mix in zip(reqs, mixed):
+        alone = srv.poll(srv.submit(bi, m, K_use=K, target=T, prec=p), n, 1, T is not None)
+        assert np.array_equal(alone["image"], mix["image"]), (n, p)
+        if T is not None:
+            assert np.array_equal(alone["grad"], mix["grad"]) and alone["loss"] == mix["loss"]
+    srv.close()
+    for b in banks:
+        b.close()
+
+
+def test_device_memory_stays_within_the_budget(L):
+    # mixed sizes and modes through 8 slots under a 1.5 GiB budget: the
+    # device memory the server holds (slot arenas with workspaces and I/O
+    # buffers), read with hipMemGetInfo while the stream runs, stays within it
+    import threading
+    import time
+
+    import torch
+    banks = [L.Bank.from_spec(W.serve_optics(n).with_(K=20)) for n in (256, 512, 1024, 2048)]
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    budget = 3 << 29
+    srv = L.Server(banks, hbm_budget=budget, max_slots=8)
+    rng = np.random.default_rng(3200)
+    masks = {n: W.as_f32_exact(W.curvilinear_mask(n, 700 + n)) for n in (256, 512, 1024, 2048)}
+    tgts = {n: W.manhattan_target(n, 800 + n) for n in (256, 512, 1024, 2048)}
+    used, stop = [], [False]
+
+    def watch():
+        while not stop[0]:
+            used.append(free0 - torch.cuda.mem_get_info()[0])
+            time.sleep(0.002)
+    th = threading.Thread(target=watch)
+    th.start()
+    tickets = []
+    for i in range(48):
+        bi = int(rng.integers(0, 4))
+        n = (256, 512, 1024, 2048)[bi]
+        tickets.append((srv.submit(bi, masks[n], K_use=int(rng.integers(10, 21)),
+                                   target=tgts[n] if i % 2 else None), n, bool(i % 2)))
+    for t, n, g in tickets:
+        assert srv.poll(t, n, 1, g) is not None
+    used.append(free0 - torch.cuda.mem_get_info()[0])
+    stop[0] = True
+    th.join()
+    srv.close()
+    slack = 64 << 20      # streams, events and allocator granularity
+    print(f"served under a {budget >> 20} MiB budget: peak device use {max(used) >> 20} MiB")
+    assert max(used) <= budget + slack
+    for b in banks:
+        b.close()
