@@ -36,6 +36,7 @@ FP32_NONPACKED_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # VALU instruction issue: one wave64 instruction per SIMD every 4 cycles, i.e. one per CU per cycle
 VALU_ISSUE_PER_S = 256 * 2.4e9
+SETTLE_S = 0.3          # untimed steady-state lead-in of each ILT leg, seconds
 SPLIT_MODES = ("f16x3", "bf16x3", "f16", "bf16")
 
 
@@ -52,7 +53,7 @@ def parse():
                     help="only run one device copy of MIB MiB (HBM counter calibration) and exit")
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests in the served stream (0: skip)")
-    ap.add_argument("--large-steps", type=int, default=5,
+    ap.add_argument("--large-steps", type=int, default=20,
                     help="timed steps of the 2048^2 and 4096^2 three-plane legs (0: skip)")
     ap.add_argument("--only", default="", help="comma list of legs: headline,mp,large,serve,cpu")
     return ap.parse_args()
@@ -212,6 +213,20 @@ class IltLeg:
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    def settle(self, fn, seconds=SETTLE_S):
+        """Untimed steps until `seconds` of wall time have passed: the device
+        raises its clocks over the first ~0.1-0.2 s under load, and the timed
+        and traced loops should see the steady state.  Returns the step count."""
+        torch = self.torch
+        t0, n = time.perf_counter(), 0
+        while True:
+            fn()
+            n += 1
+            if n % 4 == 0:
+                torch.cuda.synchronize()
+                if time.perf_counter() - t0 >= seconds:
+                    return n
+
     def traced(self, fn, steps):
         """Per-kernel (launches per step, average ms) from HIP events on the launch stream."""
         L = self.L
@@ -264,6 +279,7 @@ class IltLeg:
 def ilt_leg(L, torch, leg, steps, warmup, modes, traffic_lookup=None):
     for _ in range(warmup):
         leg.step()
+    settled = leg.settle(leg.step)
     dt = leg.timed(leg.step, steps)
     prof = leg.traced(leg.step, max(2, steps // 2))
     kern, roof = leg.kernels_and_roofline(prof, dt, traffic_lookup)
@@ -272,6 +288,7 @@ def ilt_leg(L, torch, leg, steps, warmup, modes, traffic_lookup=None):
     dtf = leg.timed(leg.forward, steps)
     out = {"value": leg.pk / dt / 1e6, "unit": UNIT, "ms_per_step": dt * 1e3,
            "forward_only": {"value": leg.pk / dtf / 1e6, "ms": dtf * 1e3},
+           "settle": {"seconds": SETTLE_S, "untimed_steps": settled},
            "kernels": kern, "roofline": roof}
     if modes:
         out["split_precision"] = split_modes(torch, leg, steps, out["value"], out["forward_only"]["value"], modes)
@@ -519,6 +536,7 @@ def main():
                    "clips": batch, "n": n, "K": K, "planes": P, "inner_grid": leg.bank.inner_grid,
                    "band": leg.bank.B},
         "forward_only": head["forward_only"],
+        "settle": head["settle"],
         "roofline": head["roofline"],
     }
     if "split_precision" in head:

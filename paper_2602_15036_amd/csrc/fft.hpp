@@ -316,7 +316,7 @@ constexpr int lds_len() { return L + pad_max(typename PadPlan<L>::M{}) * (L / 32
 // threads stay inside one wavefront use it.  Row stride (in four-byte slots
 // beyond the padded length) and per-exchange padding come from a bank model
 // of four-byte accesses (64 banks, 32 or 64 lanes a cycle), under which
-// these exchanges are free of conflicts.
+// the exchanges of the plans of at most 32 threads are free of conflicts.
 template <int L>
 struct HalfPlan {
   static constexpr bool ok = false;
@@ -334,6 +334,16 @@ template <> struct HalfPlan<384> { static constexpr bool ok = true; static const
 template <> struct HalfPlan<512> { static constexpr bool ok = true; static constexpr int extra = 32; using M = PadMults<1, 4>; };
 template <> struct HalfPlan<640> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 4, 8>; };
 template <> struct HalfPlan<768> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 4>; };
+// one transform per wavefront (the row stride does not matter): these keep
+// some two-way conflicts under the 64-lane model (none beyond the two-cycle
+// minimum under the 32-lane one).  Which passes use a plan is decided per
+// pass by the kernels.
+template <> struct HalfPlan<1024> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 2>; };
+template <> struct HalfPlan<1280> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 1, 8>; };
+template <> struct HalfPlan<1536> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<0, 1, 4>; };
+template <> struct HalfPlan<2048> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 2>; };
+template <> struct HalfPlan<2560> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 4, 0>; };
+template <> struct HalfPlan<3072> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 2>; };
 // four-byte slots of one transform's region
 template <int L>
 constexpr int lds_len_half() { return L + pad_max(typename HalfPlan<L>::M{}) * (L / 32) + HalfPlan<L>::extra; }

@@ -520,6 +520,54 @@ __device__ __forceinline__ const cf *stage_twiddles(const cf *__restrict__ tw, c
   }
 }
 
+// Exchange region of one transform of the k-loop passes, in four-byte slots:
+// the half-width exchange (real parts, then imaginary parts: half the LDS per
+// transform, twice the LDS instructions) or complex slots.  A column pass lays
+// its columns out like the rows of a row pass (T threads and one region each,
+// two regions per wavefront at T = 32), so one bank model holds for both.
+template <int Q, bool HALF>
+struct Xch {
+  static_assert(!HALF || HalfPlan<Q>::ok, "no half-width exchange plan for this length");
+  static constexpr int floats = HALF ? lds_len_half<Q>() : 2 * lds_len<Q>();
+};
+template <int Q, bool HALF, int DIR>
+__device__ __forceinline__ void xch_fft(cf (&v)[Q / FftPlan<Q>::T], float *xch, int t, const cf *tw) {
+  if constexpr (HALF)
+    fft_half<Q, DIR>(v, xch, t, tw);
+  else
+    fft<Q, DIR>(v, reinterpret_cast<cf *>(xch), t, tw);
+}
+// Which k-loop passes take the half-width exchange, as measured on the
+// workloads of each length.  Row passes: at lengths up to 768 (the complex
+// exchange held them at two workgroups per CU) and from 2560 (one); at
+// 1024..2048 the extra LDS round trip cost more than the occupancy gained
+// (the 1280-point row passes ran 20-35% slower with it).  Adjoint column
+// pass: wherever a plan exists (3-16% faster).  Forward column pass: never
+// (the 640-point pass, whose occupancy is then set by its registers, ran
+// 29% slower with it).
+template <int Q>
+struct RowHalf {
+  static constexpr bool value = HalfPlan<Q>::ok && (Q <= 768 || Q >= 2560);
+};
+template <int Q>
+struct ColAdjHalf {
+  static constexpr bool value = HalfPlan<Q>::ok;
+};
+template <int Q>
+using RowXch = Xch<Q, RowHalf<Q>::value>;
+template <int Q, int DIR>
+__device__ __forceinline__ void row_fft(cf (&v)[Q / FftPlan<Q>::T], float *xch, int t, const cf *tw) {
+  xch_fft<Q, RowHalf<Q>::value, DIR>(v, xch, t, tw);
+}
+// Exchange regions of a k-loop column block, then its staged twiddles (kept
+// eight-byte aligned).
+template <int Q, bool HALF>
+struct ColXch {
+  static constexpr int regions = ColBlock<Q>::threads / FftPlan<Q>::T;
+  static_assert((regions * Xch<Q, HALF>::floats) % 2 == 0, "twiddles must start on a complex slot");
+  static constexpr size_t bytes = size_t(regions) * Xch<Q, HALF>::floats * sizeof(float);
+};
+
 // ------------------------------------------------------------ forward column pass
 // Y_k[jt][y][c] = sum_ky Phi'_k(ky, j) Mh(ky, j) exp(+2 pi i ky y / Q), for the
 // kernels k0 .. k0 + kpb - 1 of this block: the mask-spectrum column stays in
@@ -534,8 +582,10 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_fwd(const cf *_
   bool valid;
   col_coords<Q>(g.nt, jt, c, t, valid);
   const int k0 = blockIdx.y * kpb, k1 = min(g.K, k0 + kpb), clip = blockIdx.z;
-  cf *buf = smem + (threadIdx.x / T) * lds_len<Q>();
-  const cf *tw = stage_twiddles<Q>(tw_table, smem + (ColBlock<Q>::threads / T) * lds_len<Q>());
+  using X = Xch<Q, false>;
+  float *const xbase = reinterpret_cast<float *>(smem);
+  float *xch = xbase + (threadIdx.x / T) * X::floats;
+  const cf *tw = stage_twiddles<Q>(tw_table, reinterpret_cast<cf *>(xbase + ColXch<Q, false>::regions * X::floats));
   const size_t kb = size_t(g.nt) * g.B * kC;
   const cf *ph = bank + (size_t(g.p) * g.Kbank * g.nt + jt) * g.B * kC + c;
   const cf *mh = Mh + (size_t(clip) * g.nt + jt) * g.B * kC + c;
@@ -559,7 +609,7 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_fwd(const cf *_
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = cmul(nxt[i], m[i]);
     if (k + 1 < k1) load_band(nxt, ph + (k + 1) * kb);
-    fft<Q, +1>(v, buf, t, tw);
+    xch_fft<Q, false, +1>(v, xch, t, tw);
     if (valid) {
       cf *dst = Y + ((size_t(clip) * g.K + k) * g.nt + jt) * size_t(Q) * kC + c;
       const int tt = opaque_lane(t);
@@ -580,21 +630,14 @@ template <int Q, bool PR>
 struct AdjRowWaves {
   static constexpr int value = (PR && FftPlan<Q>::T > 32 && RowWaves<Q>::value > 3) ? 3 : RowWaves<Q>::value;
 };
-// Exchange region of one row of the k-loop row passes, in four-byte slots:
-// the half-width exchange where the plan has one (half the LDS per row, so
-// twice the resident rows), else complex slots.
-template <int Q>
-struct RowXch {
-  static constexpr bool half = HalfPlan<Q>::ok;
-  static constexpr int floats = half ? lds_len_half<Q>() : 2 * lds_len<Q>();
+// The pruned row passes load the next kernel's band row while one is
+// transformed; transforms of more than 20 values per thread skip it, since
+// the second register copy would push them into AGPR spills at one wavefront
+// per SIMD (occupancy hides their latency instead).
+template <int Q, bool PR>
+struct RowPrefetch {
+  static constexpr bool value = PR && Q / FftPlan<Q>::T <= 20;
 };
-template <int Q, int DIR>
-__device__ __forceinline__ void row_fft(cf (&v)[Q / FftPlan<Q>::T], float *xch, int t, const cf *tw) {
-  if constexpr (RowXch<Q>::half)
-    fft_half<Q, DIR>(v, xch, t, tw);
-  else
-    fft<Q, DIR>(v, reinterpret_cast<cf *>(xch), t, tw);
-}
 
 // Waves per SIMD that the LDS of a 256-thread row-pass block (exchange rows
 // and staged twiddles) allows on a 160 KB CU; a register target above it buys
@@ -613,8 +656,21 @@ struct CapWaves {
 // I_Q(y, x) = dose * sum_k |sum_kx Y_k(y, kx) exp(+2 pi i kx x / Q)|^2.
 // OUT 0 (Q == N): image / resist epilogue.  OUT 1 (Q < N): forward row DFT of
 // the I_Q row, keep |gx| <= 2b, scale dose/Q^2, store tiled [ntD][Q][kC] in Ib.
+// The 640-point forward row pass (the 1024^2 workloads' inner grid) runs at
+// five wavefronts per SIMD without the band-row prefetch: its 1280
+// workgroups per 16 clips then fit the device at once, and it ran 5% faster
+// than at four with the prefetch.
+template <int Q>
+struct FwdRowWaves {
+  static constexpr int value = Q == 640 ? 5 : RowWaves<Q>::value;
+};
+template <int Q, bool PR>
+struct FwdPrefetch {
+  static constexpr bool value = Q != 640 && RowPrefetch<Q, PR>::value;
+};
+
 template <int Q, int OUT, bool PR>
-__global__ __launch_bounds__(256, (CapWaves<RowWaves<Q>::value, Q>::value)) void k_pass_x_fwd(const cf *__restrict__ Y, Epi ep, cf *__restrict__ Ib, Geo g,
+__global__ __launch_bounds__(256, (CapWaves<FwdRowWaves<Q>::value, Q>::value)) void k_pass_x_fwd(const cf *__restrict__ Y, Epi ep, cf *__restrict__ Ib, Geo g,
                                                     const cf *__restrict__ tw_table) {
   constexpr int T = FftPlan<Q>::T, E = Q / T, RPB = 256 / T;
   extern __shared__ cf smem[];
@@ -632,10 +688,10 @@ __global__ __launch_bounds__(256, (CapWaves<RowWaves<Q>::value, Q>::value)) void
   // pruned variant: the band row of kernel k + 1 (half the elements) is
   // loaded while kernel k is transformed
   cf nxt[E];
-  if (PR) io.load(nxt, yc);
+  if (FwdPrefetch<Q, PR>::value) io.load(nxt, yc);
   for (int k = 0; k < g.K; ++k) {
     cf v[E];
-    if (PR) {
+    if (FwdPrefetch<Q, PR>::value) {
 #pragma unroll
       for (int i = 0; i < E; ++i) v[i] = nxt[i];
       if (k + 1 < g.K) io.load(nxt, yc + (k + 1) * kstride);
@@ -703,10 +759,10 @@ __global__ __launch_bounds__(256, (CapWaves<AdjRowWaves<Q, PR>::value, Q>::value
   // loaded while kernel k is transformed (each row is read completely before
   // this wavefront overwrites it)
   cf nxt[E];
-  if (PR) io.load(nxt, yc);
+  if (RowPrefetch<Q, PR>::value) io.load(nxt, yc);
   for (int k = 0; k < g.K; ++k) {
     cf v[E];
-    if (PR) {
+    if (RowPrefetch<Q, PR>::value) {
 #pragma unroll
       for (int i = 0; i < E; ++i) v[i] = nxt[i];
       if (k + 1 < g.K) io.load(nxt, yc + (k + 1) * kstride);
@@ -736,8 +792,11 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *_
   bool valid;
   col_coords<Q>(g.nt, jt, c, t, valid);
   const int kc = blockIdx.y, clip = blockIdx.z;
-  cf *buf = smem + (threadIdx.x / T) * lds_len<Q>();
-  const cf *tw = stage_twiddles<Q>(tw_table, smem + (ColBlock<Q>::threads / T) * lds_len<Q>());
+  constexpr bool H = ColAdjHalf<Q>::value;
+  using X = Xch<Q, H>;
+  float *const xbase = reinterpret_cast<float *>(smem);
+  float *xch = xbase + (threadIdx.x / T) * X::floats;
+  const cf *tw = stage_twiddles<Q>(tw_table, reinterpret_cast<cf *>(xbase + ColXch<Q, H>::regions * X::floats));
   cf acc[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) acc[i] = cmake(0.f, 0.f);
@@ -778,7 +837,7 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *_
         if (r >= 0) w[i] = ph[r * kC];
       }
     }
-    fft<Q, -1>(v, buf, t, tw);
+    xch_fft<Q, H, -1>(v, xch, t, tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       if (PR && never_in_band<Q>(i)) continue;
@@ -1362,7 +1421,7 @@ template <int Q>
 int pass_y_fwd_q(const cf *bank, const cf *Mh, cf *Y, const PassGeo &pg, const cf *twQ, int nclips,
                  hipStream_t s) {
   Geo g = to_geo(pg);
-  constexpr size_t sh = col_lds<Q>() + dev::TwLds<Q>::bytes;
+  constexpr size_t sh = dev::ColXch<Q, false>::bytes + dev::TwLds<Q>::bytes;
   // kernels per block: enough blocks to fill the device (~2560), the rest
   // looped inside a block
   const int per_k = col_blocks<Q>(g.nt) * nclips;
@@ -1431,7 +1490,7 @@ template <int Q>
 int pass_y_adj_q(const cf *V, const cf *bank, double2 *part, const PassGeo &pg, const cf *twQ, int nclips,
                  hipStream_t s) {
   Geo g = to_geo(pg);
-  constexpr size_t sh = col_lds<Q>() + dev::TwLds<Q>::bytes;
+  constexpr size_t sh = dev::ColXch<Q, dev::ColAdjHalf<Q>::value>::bytes + dev::TwLds<Q>::bytes;
   const dim3 grid(col_blocks<Q>(g.nt), g.KC, nclips);
   if (dev::prunable<Q>(g.b))
     return launch("pass_y_adj", KPTR(dev::k_pass_y_adj<Q, true>), grid, sh, s, [&] {
