@@ -98,6 +98,8 @@ def launch_bytes(name, g, c):
         return c * 8 * D * (D + N)
     if name == "up_rows":
         return c * (8 * N * D + 12 * N * N)
+    if name == "image_residual_rows":       # image band in, image out, target in, residual band out
+        return c * (16 * N * D + 8 * N * N)
     if name == "down_rows":
         return c * (4 * N * N + 8 * N * D)
     if name == "down_cols_n":

@@ -415,7 +415,9 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
   L.b_S1 = align256(size_t(g.nt) * N * kTileCols * sizeof(float2));
   L.b_Mh = align256(size_t(g.nt) * g.B * kTileCols * sizeof(float2));
   L.b_Y = align256(size_t(K_use) * g.nt * Q * kTileCols * sizeof(float2));
-  L.b_G = (grad && fused) ? align256(N * N * sizeof(float)) : 0;
+  // the residual G on the N grid is only stored where the adjoint row pass reads it
+  // (no resampling); the resampled step keeps it on chip
+  L.b_G = (grad && fused && !resample) ? align256(N * N * sizeof(float)) : 0;
   L.b_part = grad ? align256(size_t(g.P) * g.KC * g.nt * g.B * kTileCols * sizeof(double2)) : 0;
   L.b_loss = (grad && fused) ? align256(size_t(g.P) * L.nblk * sizeof(double)) : 0;
   L.b_X = resample ? align256(std::max(N, Q) * g.Dp * sizeof(float2)) : 0;
@@ -549,7 +551,9 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
       // resist kernel of Eq. 5 on the intensity band: R = I (x) K_resist
       LITHO_TRY(run_band_gauss(X2, h2, g.ntD, double(g.N), blur, band_clip, n, s));
       LITHO_TRY(run_col_fft("up_cols_n", g.N, +1, X2, X1, g.ntD, h2, -1, twN, 1.0f, n, s));
-      if (ep.image || ep.target)
+      if (grad && fused)  // image, loss and the residual's row DFT to the band, in place in X1
+        LITHO_TRY(run_rows_image_residual("image_residual_rows", g.N, X1, h2, g.Dp, ep, g, twN, 1.0f, n, s));
+      else if (ep.image || ep.target)
         LITHO_TRY(run_rows_inv_real("up_rows", g.N, X1, h2, g.Dp, nullptr, ep, g, twN, 1.0f, n, s));
     }
     if (!grad) continue;
@@ -558,8 +562,9 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
     if (!resample) {
       LITHO_TRY(run_pass_x_adj(Y, Gp, gstride, nullptr, g, twQ, n, s));
     } else {
-      // G low-passed to |f| <= 2b and sampled on the Q grid (scaled by 1/Q^2)
-      LITHO_TRY(run_rows_fwd_real("down_rows", g.N, Gp, gstride, X1, h2, g.Dp, twN, 1.0f, n, s));
+      // G low-passed to |f| <= 2b and sampled on the Q grid (scaled by 1/Q^2);
+      // the fused step's row DFT of G was done by the image row pass
+      if (!fused) LITHO_TRY(run_rows_fwd_real("down_rows", g.N, Gp, gstride, X1, h2, g.Dp, twN, 1.0f, n, s));
       LITHO_TRY(run_col_fft("down_cols_n", g.N, -1, X1, X2, g.ntD, -1, h2, twN, 1.0f, n, s));
       // dL/dI = K_resist (x) dL/dR (the Gaussian is symmetric)
       LITHO_TRY(run_band_gauss(X2, h2, g.ntD, double(g.N), blur, band_clip, n, s));

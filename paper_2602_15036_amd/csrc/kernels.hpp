@@ -51,6 +51,12 @@ int run_rows_fwd_real(const char *name, int L, const float *in, size_t in_clip, 
                       const cf2 *tw, float scale, int nclips, hipStream_t s);
 int run_rows_inv_real(const char *name, int L, const cf2 *in, int h, int Wp, float *out, const EpiPtrs &ep,
                       const PassGeo &g, const cf2 *tw, float scale, int nclips, hipStream_t s);
+// The ILT step's row pass on the N grid with the residual kept on chip: image
+// band rows (h, Wp) -> image / resist / loss epilogue (ep.target required) ->
+// the residual's forward row DFT, its band |gx| <= h stored in place of the
+// image band rows.  Loss partials per block as run_rows_inv_real's MODE 1.
+int run_rows_image_residual(const char *name, int L, cf2 *band, int h, int Wp, const EpiPtrs &ep,
+                            const PassGeo &g, const cf2 *tw, float scale, int nclips, hipStream_t s);
 // Same as run_rows_inv_real without epilogue, written as 1 where scale Re v >= thr, else 0.
 int run_rows_inv_thresh(const char *name, int L, const cf2 *in, int h, int Wp, float *out, double thr,
                         const cf2 *tw, float scale, int nclips, hipStream_t s);
