@@ -306,6 +306,40 @@ constexpr int pad_max(PadMults<Ms...>) {
 
 template <int M>
 __device__ __forceinline__ int lpad(int i) { return i + M * (i >> 5); }
+constexpr int lpad_c(int i, int M) { return i + M * (i >> 5); }
+
+// Exchange addressing.  Output r of butterfly mb of lane t in a pass of radix
+// R after radices multiplying to S goes to position wpos(t, mb, r); lane t
+// reads back positions t + T*i.  For every plan here the padded address of
+// each (mb, r), and of each i, is the lane's own (0, 0) (or i = 0) address
+// plus an offset that is the same for all lanes (checked at compile time
+// below), so an exchange costs one per-lane base and immediate LDS offsets
+// rather than an address computation per value.
+template <int T, int R, int S>
+constexpr int wpos(int t, int mb, int r) {
+  return ((t + T * mb) / S) * S * R + (t + T * mb) % S + r * S;
+}
+template <int T, int R, int S, int NB, int M>
+constexpr bool lane_uniform_writes() {
+  for (int t = 0; t < T; ++t)
+    for (int mb = 0; mb < NB; ++mb)
+      for (int r = 0; r < R; ++r)
+        if (lpad_c(wpos<T, R, S>(t, mb, r), M) - lpad_c(wpos<T, R, S>(t, 0, 0), M) !=
+            lpad_c(wpos<T, R, S>(0, mb, r), M) - lpad_c(wpos<T, R, S>(0, 0, 0), M))
+          return false;
+  return true;
+}
+template <int T, int E, int M>
+constexpr bool lane_uniform_reads() {
+  for (int t = 0; t < T; ++t)
+    for (int i = 0; i < E; ++i)
+      if (lpad_c(t + T * i, M) - lpad_c(t, M) != lpad_c(T * i, M)) return false;
+  return true;
+}
+template <int T, int R, int S, int M>
+constexpr int woff(int mb, int r) {
+  return lpad_c(wpos<T, R, S>(0, mb, r), M) - lpad_c(wpos<T, R, S>(0, 0, 0), M);
+}
 template <int L>
 constexpr int lds_len() { return L + pad_max(typename PadPlan<L>::M{}) * (L / 32) + 4; }
 
@@ -429,6 +463,10 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ b
     if constexpr (LAST) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[mb + r * NB] = u[r];
+    } else if constexpr (lane_uniform_writes<T, R, S, NB, M>()) {
+      cf *wb = buf + lpad<M>(wpos<T, R, S>(t, 0, 0));
+#pragma unroll
+      for (int r = 0; r < R; ++r) wb[woff<T, R, S, M>(mb, r)] = u[r];
     } else {
       const int base = (j / S) * S * R + (j % S);
 #pragma unroll
@@ -437,8 +475,14 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ b
   }
   if constexpr (!LAST) {
     xsync<T>();
+    if constexpr (lane_uniform_reads<T, E, M>()) {
+      const cf *rb = buf + lpad<M>(t);
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = buf[lpad<M>(t + T * i)];
+      for (int i = 0; i < E; ++i) v[i] = rb[lpad_c(T * i, M)];
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = buf[lpad<M>(t + T * i)];
+    }
     xsync<T>();
   }
 }
@@ -473,25 +517,25 @@ __device__ __forceinline__ void stockham_pass_half(cf (&v)[L / T], float *__rest
     for (int r = 0; r < R; ++r) v[mb + r * NB] = u[r];
   }
   if constexpr (!LAST) {
+    static_assert(lane_uniform_writes<T, R, S, NB, M>() && lane_uniform_reads<T, E, M>(),
+                  "half-width exchange plans use lane-uniform offsets");
+    float *wb = buf + lpad<M>(wpos<T, R, S>(t, 0, 0));
+    const float *rb = buf + lpad<M>(t);
 #pragma unroll
-    for (int mb = 0; mb < NB; ++mb) {
-      const int j = t + T * mb, base = (j / S) * S * R + (j % S);
+    for (int mb = 0; mb < NB; ++mb)
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lpad<M>(base + r * S)] = v[mb + r * NB].x;
-    }
+      for (int r = 0; r < R; ++r) wb[woff<T, R, S, M>(mb, r)] = v[mb + r * NB].x;
     xsync<T>();
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i].x = buf[lpad<M>(t + T * i)];
+    for (int i = 0; i < E; ++i) v[i].x = rb[lpad_c(T * i, M)];
     xsync<T>();
 #pragma unroll
-    for (int mb = 0; mb < NB; ++mb) {
-      const int j = t + T * mb, base = (j / S) * S * R + (j % S);
+    for (int mb = 0; mb < NB; ++mb)
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lpad<M>(base + r * S)] = v[mb + r * NB].y;
-    }
+      for (int r = 0; r < R; ++r) wb[woff<T, R, S, M>(mb, r)] = v[mb + r * NB].y;
     xsync<T>();
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i].y = buf[lpad<M>(t + T * i)];
+    for (int i = 0; i < E; ++i) v[i].y = rb[lpad_c(T * i, M)];
     xsync<T>();
   }
 }
