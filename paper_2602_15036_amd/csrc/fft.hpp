@@ -346,8 +346,9 @@ constexpr int lds_len() { return L + pad_max(typename PadPlan<L>::M{}) * (L / 32
 // Half-width exchange: the real parts of a transform cross the LDS first,
 // then the imaginary parts, through one region of four-byte slots, which
 // halves the LDS a transform holds (and so raises the occupancy of the
-// LDS-bound row passes) for twice the LDS instructions.  Only plans whose
-// threads stay inside one wavefront use it.  Row stride (in four-byte slots
+// LDS-bound row passes) for twice the LDS instructions.  The exchanges are
+// ordered by the same waits as the complex ones (within a wavefront up to 64
+// threads, block barriers beyond).  Row stride (in four-byte slots
 // beyond the padded length) and per-exchange padding come from a bank model
 // of four-byte accesses (64 banks, 32 or 64 lanes a cycle), under which
 // the exchanges of the plans of at most 32 threads are free of conflicts.
@@ -378,6 +379,9 @@ template <> struct HalfPlan<1536> { static constexpr bool ok = true; static cons
 template <> struct HalfPlan<2048> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 2>; };
 template <> struct HalfPlan<2560> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 4, 0>; };
 template <> struct HalfPlan<3072> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 2>; };
+// two wavefronts per transform (block barriers); two-way conflicts remain in
+// the first exchange under the 64-lane model
+template <> struct HalfPlan<4096> { static constexpr bool ok = true; static constexpr int extra = 0; using M = PadMults<1, 2>; };
 // four-byte slots of one transform's region
 template <int L>
 constexpr int lds_len_half() { return L + pad_max(typename HalfPlan<L>::M{}) * (L / 32) + HalfPlan<L>::extra; }
@@ -495,7 +499,6 @@ __device__ __forceinline__ void stockham_pass_half(cf (&v)[L / T], float *__rest
   constexpr int E = L / T;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide the per-thread count");
-  static_assert(T <= 64, "the half-width exchange orders its two halves within one wavefront");
   const cf *twp = opaque(tw);
 #pragma unroll
   for (int mb = 0; mb < NB; ++mb) {

@@ -524,6 +524,31 @@ __global__ __launch_bounds__(256) void k_rows_image_residual(cf *band, int h, in
   if (threadIdx.x == 0) ep.loss_part[(size_t(clip) * g.P + g.p) * gridDim.x + blockIdx.x] = s;
 }
 
+// Exchange region of one transform, in four-byte slots: the half-width
+// exchange (real parts, then imaginary parts: half the LDS per transform,
+// twice the LDS instructions) or complex slots.  A column pass lays its
+// columns out like the rows of a row pass (T threads and one region each, two
+// regions per wavefront at T = 32), so one bank model holds for both.
+template <int Q, bool HALF>
+struct Xch {
+  static_assert(!HALF || HalfPlan<Q>::ok, "no half-width exchange plan for this length");
+  static constexpr int floats = HALF ? lds_len_half<Q>() : 2 * lds_len<Q>();
+};
+template <int Q, bool HALF, int DIR>
+__device__ __forceinline__ void xch_fft(cf (&v)[Q / FftPlan<Q>::T], float *xch, int t, const cf *tw) {
+  if constexpr (HALF)
+    fft_half<Q, DIR>(v, xch, t, tw);
+  else
+    fft<Q, DIR>(v, reinterpret_cast<cf *>(xch), t, tw);
+}
+// The plain column transforms (mask spectrum, resampling, low-pass) take the
+// half-width exchange from length 2560 on, where four complex regions held
+// them to one workgroup per CU.
+template <int L>
+struct ColFftHalf {
+  static constexpr bool value = HalfPlan<L>::ok && L >= 2560;
+};
+
 // ------------------------------------------------------------ column passes
 // A column pass runs one length-L transform per tile column.  A block holds
 // ColBlock<L>::tiles tiles (4 columns each, T threads per column); every
@@ -590,7 +615,7 @@ __global__ __launch_bounds__(ColBlock<L>::threads) void k_col_fft(const cf *__re
   bool valid;
   col_coords<L>(nt, jt, c, t, valid);
   const int clip = blockIdx.y;
-  cf *buf = smem + (threadIdx.x / T) * lds_len<L>();
+  float *xch = reinterpret_cast<float *>(smem) + (threadIdx.x / T) * Xch<L, ColFftHalf<L>::value>::floats;
   const int rin = in_h < 0 ? L : 2 * in_h + 1;
   const int rout = out_h < 0 ? L : 2 * out_h + 1;
   // buffer views of this clip's arrays; positions off the band read as zero
@@ -605,7 +630,7 @@ __global__ __launch_bounds__(ColBlock<L>::threads) void k_col_fft(const cf *__re
     const int r = in_h < 0 ? pos : band_row_of(pos, L, in_h);
     v[i] = buf_load(src, r >= 0 ? (in0 + unsigned(r) * kC) * unsigned(sizeof(cf)) : kOffBand);
   }
-  fft<L, DIR>(v, buf, t, tw);
+  xch_fft<L, ColFftHalf<L>::value, DIR>(v, xch, t, tw);
   if (!valid) return;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
@@ -636,23 +661,6 @@ __device__ __forceinline__ const cf *stage_twiddles(const cf *__restrict__ tw, c
   }
 }
 
-// Exchange region of one transform of the k-loop passes, in four-byte slots:
-// the half-width exchange (real parts, then imaginary parts: half the LDS per
-// transform, twice the LDS instructions) or complex slots.  A column pass lays
-// its columns out like the rows of a row pass (T threads and one region each,
-// two regions per wavefront at T = 32), so one bank model holds for both.
-template <int Q, bool HALF>
-struct Xch {
-  static_assert(!HALF || HalfPlan<Q>::ok, "no half-width exchange plan for this length");
-  static constexpr int floats = HALF ? lds_len_half<Q>() : 2 * lds_len<Q>();
-};
-template <int Q, bool HALF, int DIR>
-__device__ __forceinline__ void xch_fft(cf (&v)[Q / FftPlan<Q>::T], float *xch, int t, const cf *tw) {
-  if constexpr (HALF)
-    fft_half<Q, DIR>(v, xch, t, tw);
-  else
-    fft<Q, DIR>(v, reinterpret_cast<cf *>(xch), t, tw);
-}
 // Which k-loop passes take the half-width exchange, as measured on the
 // workloads of each length.  Row passes: at lengths up to 768 (the complex
 // exchange held them at two workgroups per CU) and from 2560 (one); at
@@ -1546,7 +1554,8 @@ template <int L, int DIR>
 int col_fft_l(const char *name, const cf *in, cf *out, int nt, int in_h, int out_h, const cf *tw, float scale,
               int nclips, hipStream_t s) {
   const size_t rin = in_h < 0 ? L : 2 * in_h + 1, rout = out_h < 0 ? L : 2 * out_h + 1;
-  constexpr size_t sh = col_lds<L>();
+  constexpr size_t sh = size_t(dev::ColBlock<L>::threads / FftPlan<L>::T) *
+                        dev::Xch<L, dev::ColFftHalf<L>::value>::floats * sizeof(float);
   const dim3 grid(col_blocks<L>(nt), nclips);
   return launch(name, KPTR(dev::k_col_fft<L, DIR>), grid, sh, s, [&] {
     hipLaunchKernelGGL((dev::k_col_fft<L, DIR>), grid, dim3(dev::ColBlock<L>::threads), sh, s, in, out, nt, in_h,
