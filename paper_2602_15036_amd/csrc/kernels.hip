@@ -542,11 +542,12 @@ __device__ __forceinline__ void xch_fft(cf (&v)[Q / FftPlan<Q>::T], float *xch, 
     fft<Q, DIR>(v, reinterpret_cast<cf *>(xch), t, tw);
 }
 // The plain column transforms (mask spectrum, resampling, low-pass) take the
-// half-width exchange from length 2560 on, where four complex regions held
-// them to one workgroup per CU.
+// half-width exchange at the lengths where the row passes do: up to 768 (the
+// 640-point resampling columns 8% faster) and from 2560, where four complex
+// regions held them to one workgroup per CU; at 1024 it cost 6%.
 template <int L>
 struct ColFftHalf {
-  static constexpr bool value = HalfPlan<L>::ok && L >= 2560;
+  static constexpr bool value = HalfPlan<L>::ok && (L <= 768 || L >= 2560);
 };
 
 // ------------------------------------------------------------ column passes
@@ -578,26 +579,31 @@ __device__ __forceinline__ void col_coords(int nt, int &jt, int &c, int &t, bool
   col_coords<L>(blockIdx.x, nt, jt, c, t, valid);
 }
 
-// Workgroup coordinates of the adjoint column pass over its grid (column
-// block, k-chunk, clip), permuted so that consecutive workgroups of one XCD
-// take the same column block and k-chunk for consecutive clips.  Workgroups
-// are handed to the 8 XCDs in turn (linear id, x fastest), and these ones read
-// the same bank tiles, which then come from that XCD's L2 instead of once per
-// clip from HBM (3% faster at 16 x 1024^2; the forward column pass, whose
-// output stream dominates, ran 6% slower with it and keeps the plain order).
-// The map is a permutation of the grid: results do not depend on it.
+// Workgroup coordinates of a column pass whose grid z encodes (i, clip) as
+// z = i + inner * clip, permuted so that consecutive workgroups of one XCD
+// take the same (x, y, i) for consecutive clips.  Workgroups are handed to the
+// 8 XCDs in turn (linear id, x fastest), and these ones read the same bank
+// tiles, which then come from that XCD's L2 instead of once per clip from HBM.
+// Used by the adjoint column pass (3% faster at 16 x 1024^2); the forward
+// column pass, whose output stream dominates, ran 6% slower with it, and the
+// split GEMM passes (bank tiles read through LDS staging) gained nothing, so
+// they keep the plain order.  The map is a permutation of the grid: results
+// do not depend on it.
 struct BlockXYZ {
   int x, y, z;
 };
-__device__ __forceinline__ BlockXYZ clip_major_on_xcds() {
+__device__ __forceinline__ BlockXYZ clip_major_on_xcds(int inner) {
   constexpr int kXcds = 8;
-  const int nx = gridDim.x, ny = gridDim.y, nz = gridDim.z;
+  const int nx = gridDim.x, ny = gridDim.y, nz = gridDim.z, clips = nz / inner;
   const int n = nx * ny * nz;
   int lin = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
   const int full = n - n % kXcds;
   if (lin < full) lin = (lin % kXcds) * (full / kXcds) + lin / kXcds;
-  const int r = lin / nz;
-  return BlockXYZ{r % nx, r / nx, lin % nz};
+  const int clip = lin % clips;
+  int r = lin / clips;
+  const int x = r % nx;
+  r /= nx;
+  return BlockXYZ{x, r % ny, r / ny + inner * clip};
 }
 
 // For each tile column: a length-L DFT along the rows.  Input rows are either
@@ -914,7 +920,7 @@ __global__ __launch_bounds__(ColBlock<Q>::threads) void k_pass_y_adj(const cf *_
   extern __shared__ cf smem[];
   int jt, c, t;
   bool valid;
-  const BlockXYZ bid = clip_major_on_xcds();
+  const BlockXYZ bid = clip_major_on_xcds(1);
   col_coords<Q>(bid.x, g.nt, jt, c, t, valid);
   const int kc = bid.y, clip = bid.z;
   constexpr bool H = ColAdjHalf<Q>::value;
