@@ -154,14 +154,21 @@ int set_inner_grid(litho_bank *bk, int q) {
     return LITHO_E_INVALID;
   }
   std::lock_guard<std::mutex> lk(bk->mu);
-  bool tables = false;
+  bool tables = bk->d_rowtw != nullptr;
   for (void *t : bk->d_gemm) tables = tables || t;
+  for (void *t : bk->d_rowmma) tables = tables || t;
   if ((bk->d_twQ && bk->d_twQ != bk->d_twN) || tables) LITHO_HIP_TRY(hipDeviceSynchronize());
   if (bk->d_twQ && bk->d_twQ != bk->d_twN) (void)hipFree(bk->d_twQ);
   for (void *&t : bk->d_gemm) {
     if (t) (void)hipFree(t);
     t = nullptr;
   }
+  for (void *&t : bk->d_rowmma) {
+    if (t) (void)hipFree(t);
+    t = nullptr;
+  }
+  if (bk->d_rowtw) (void)hipFree(bk->d_rowtw);
+  bk->d_rowtw = nullptr;
   bk->d_twQ = nullptr;
   bk->Q = q;
   if (q == h.n) {
@@ -191,6 +198,39 @@ static int gemm_table(litho_bank *bk, bool adj, bool bf16, const void **out) {
     LITHO_HIP_TRY(hipMemcpy(t, tab.data(), tab.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
   }
   *out = t;
+  return LITHO_OK;
+}
+
+// Operand fragments and twiddles of the two-stage row transform for the
+// bank's inner grid, uploaded on first use.
+static int row_mfma_table(litho_bank *bk, bool bf16, const void **tab, const float2 **twl) {
+  std::lock_guard<std::mutex> lk(bk->mu);
+  void *&t = bk->d_rowmma[bf16 ? 1 : 0];
+  if (!t || !bk->d_rowtw) {
+    std::vector<uint16_t> frag;
+    std::vector<float2> tw;
+    fill_row_mfma_table(bk->Q, bf16, frag, tw);
+    if (!t) {
+      if (hipMalloc(&t, frag.size() * sizeof(uint16_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        t = nullptr;
+        set_error("litho: cannot allocate the row-transform operand table");
+        return LITHO_E_NOMEM;
+      }
+      LITHO_HIP_TRY(hipMemcpy(t, frag.data(), frag.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    }
+    if (!bk->d_rowtw) {
+      if (hipMalloc(&bk->d_rowtw, tw.size() * sizeof(float2)) != hipSuccess) {
+        (void)hipGetLastError();
+        bk->d_rowtw = nullptr;
+        set_error("litho: cannot allocate the row-transform twiddles");
+        return LITHO_E_NOMEM;
+      }
+      LITHO_HIP_TRY(hipMemcpy(bk->d_rowtw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+    }
+  }
+  *tab = t;
+  *twl = bk->d_rowtw;
   return LITHO_OK;
 }
 
@@ -364,6 +404,9 @@ extern "C" void litho_kernels_free(litho_bank_t *bk) {
   if (bk->d_twQ && bk->d_twQ != bk->d_twN) (void)hipFree(bk->d_twQ);
   for (void *t : bk->d_gemm)
     if (t) (void)hipFree(t);
+  for (void *t : bk->d_rowmma)
+    if (t) (void)hipFree(t);
+  if (bk->d_rowtw) (void)hipFree(bk->d_rowtw);
   if (bk->d_twN) (void)hipFree(bk->d_twN);
   if (bk->d_phi) (void)hipFree(bk->d_phi);
   delete bk;
@@ -390,13 +433,21 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
   g.Dp = (g.D + kTileCols - 1) / kTileCols * kTileCols;
   g.ntD = g.Dp / kTileCols;
   g.K = K_use; g.Kbank = h.K; g.P = h.n_focus; g.dose = h.dose;
+  // a resist blur acts on the intensity band, so it takes the resampling route
+  // even when the per-kernel transforms run on the full grid
+  const bool resample = g.Q != g.N || (blur && fused && grad);
+  L.resample = resample;
+  // split modes on inner grids 32 P (P <= 32) of the resampled route: the
+  // forward row pass as two MFMA stages, every column pass in FP32; other
+  // inner grids: the band DFT-GEMM column passes
+  L.row_mfma = prec != LITHO_PREC_FP32 && g.Q != g.N && row_mfma_ok(g.Q, g.N);
   // k-chunks of the adjoint column pass: enough blocks to fill the device
   // (~2048: eight per CU; more chunks only add FP64 partials for the gradient
   // columns to read), each chunk summing kper kernels in FP32 before the FP64
   // reduction.  The GEMM form has one workgroup per 32-column block of the
   // band (~1024).
   {
-    const bool gemm = prec != LITHO_PREC_FP32;
+    const bool gemm = prec != LITHO_PREC_FP32 && !L.row_mfma;
     const size_t units = gemm ? size_t(adj_gemm_blocks(g.Bp, g.B)) * batch : size_t(g.nt) * batch;
     const size_t target = gemm ? 1024 : 2048;
     const int want = int((target + units - 1) / units);
@@ -404,10 +455,6 @@ CallLayout plan_call(const litho_bank *bk, int batch, int K_use, bool grad, bool
     g.kper = (K_use + kc - 1) / kc;
     g.KC = (K_use + g.kper - 1) / g.kper;
   }
-  // a resist blur acts on the intensity band, so it takes the resampling route
-  // even when the per-kernel transforms run on the full grid
-  const bool resample = g.Q != g.N || (blur && fused && grad);
-  L.resample = resample;
   // loss partials come from the row pass that applies the resist (N grid):
   // one per block; with resampling that pass takes two rows per transform
   L.nblk = resample ? (g.N / (256 / pass_threads(g.N)) + 1) / 2 : g.N / (256 / pass_threads(g.N));
@@ -489,7 +536,8 @@ int plane_streams(litho_bank *bk, hipStream_t s, int count, hipStream_t *side, h
 // Forward (and optionally adjoint) over one chunk of clips.
 int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, int n, const float *target,
               const float *grad_image, float *image, double *loss, float *grad_mask, bool grad, hipStream_t s,
-              const CallOpts &o, int prec, const void *gemm_fwd, const void *gemm_adj) {
+              const CallOpts &o, int prec, const void *gemm_fwd, const void *gemm_adj, const void *row_tab,
+              const float2 *row_tw) {
   PassGeo g = L.g;
   g.slope = o.slope;
   g.thr = o.thr;
@@ -539,14 +587,17 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
     ep.loss_part = lossp;
     g.p = pl;
     g.pw = plane_w ? plane_w[pl] : 1.0;
-    if (prec == LITHO_PREC_FP32)
+    if (prec == LITHO_PREC_FP32 || L.row_mfma)
       LITHO_TRY(run_pass_y_fwd(bk->d_phi, Mh, Y, g, twQ, n, s));
     else
       LITHO_TRY(run_pass_y_fwd_mfma(bk->d_phi, Mh, Y, g, gemm_fwd, prec, n, s));
     if (!resample) {
       LITHO_TRY(run_pass_x_fwd(Y, ep, nullptr, g, twQ, n, s));
     } else {
-      LITHO_TRY(run_pass_x_fwd(Y, EpiPtrs{}, X1, g, twQ, n, s));
+      if (L.row_mfma)
+        LITHO_TRY(run_pass_x_fwd_mfma(Y, X1, g, row_tab, row_tw, twQ, prec, n, s));
+      else
+        LITHO_TRY(run_pass_x_fwd(Y, EpiPtrs{}, X1, g, twQ, n, s));
       LITHO_TRY(run_col_fft("up_cols_q", g.Q, -1, X1, X2, g.ntD, -1, h2, twQ, 1.0f, n, s));
       // resist kernel of Eq. 5 on the intensity band: R = I (x) K_resist
       LITHO_TRY(run_band_gauss(X2, h2, g.ntD, double(g.N), blur, band_clip, n, s));
@@ -572,7 +623,7 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
                             float(1.0 / (double(g.Q) * double(g.Q))), n, s));
       LITHO_TRY(run_pass_x_adj(Y, nullptr, 0, X1, g, twQ, n, s));
     }
-    if (prec == LITHO_PREC_FP32)
+    if (prec == LITHO_PREC_FP32 || L.row_mfma)
       LITHO_TRY(run_pass_y_adj(Y, bk->d_phi, part, g, twQ, n, s));
     else
       LITHO_TRY(run_pass_y_adj_mfma(Y, bk->d_phi, part, g, gemm_adj, prec, n, s));
@@ -635,13 +686,18 @@ int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, c
   }
   o.p0 = p0;
   o.p1 = p1;
-  const void *gemm_fwd = nullptr, *gemm_adj = nullptr;
+  CallLayout L = plan_call(bk, batch, K_use, grad, fused, prec, o.blur_sigma > 0.0);
+  const void *gemm_fwd = nullptr, *gemm_adj = nullptr, *row_tab = nullptr;
+  const float2 *row_tw = nullptr;
   if (prec != LITHO_PREC_FP32) {
     const bool bf = prec == LITHO_PREC_BF16X3 || prec == LITHO_PREC_BF16;
-    LITHO_TRY(gemm_table(bk, false, bf, &gemm_fwd));
-    if (grad) LITHO_TRY(gemm_table(bk, true, bf, &gemm_adj));
+    if (L.row_mfma) {
+      LITHO_TRY(row_mfma_table(bk, bf, &row_tab, &row_tw));
+    } else {
+      LITHO_TRY(gemm_table(bk, false, bf, &gemm_fwd));
+      if (grad) LITHO_TRY(gemm_table(bk, true, bf, &gemm_adj));
+    }
   }
-  CallLayout L = plan_call(bk, batch, K_use, grad, fused, prec, o.blur_sigma > 0.0);
   char *ws = nullptr;
   if (ext_ws) {
     // the caller's buffer (a serve slot's arena): one clip at a time if needed
@@ -662,7 +718,7 @@ int image_grad_impl(litho_bank *bk, const float *d_mask, int batch, int K_use, c
                         d_grad_image ? d_grad_image + size_t(c0) * P * NN : nullptr,
                         d_image ? d_image + size_t(c0) * P * NN : nullptr, d_loss ? d_loss + c0 : nullptr,
                         d_grad_mask ? d_grad_mask + size_t(c0) * NN : nullptr, grad, s, o, prec, gemm_fwd,
-                        gemm_adj));
+                        gemm_adj, row_tab, row_tw));
   }
   return LITHO_OK;
 }

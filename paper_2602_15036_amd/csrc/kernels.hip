@@ -1422,6 +1422,158 @@ __global__ __launch_bounds__(64 * NW) void k_pass_y_adj_mfma(const cf *__restric
   }
 }
 
+// ------------------------------------------------------------ forward row pass, two MFMA stages
+// The band-limited inverse row transform of the forward pass as two dense DFT
+// stages on the matrix cores, for inner grids Q = 32 P with P <= 32.  With
+// f = f0 + P f1' (0 <= f0 < P, -8 <= f1' < 8; every |f| <= b < Q/4 is one of
+// these) and q = r + 32 s (0 <= r < 32, 0 <= s < P), w = exp(2 pi i / Q):
+//   E_k(y, r + 32 s) = sum_f0 w^(f0 r) exp(2 pi i f0 s / P) sum_f1' exp(2 pi i f1' r / 32) Y_k(y, f)
+// Stage 1 is one 32x32x16 K-step per real product (D1[f0][r], f1 = f1' + 8 as
+// K), then the twiddle w^(f0 r) in FP32, then stage 2 contracts f0 (one or two
+// K-steps, D2[r][s]).  Stage 1's accumulator registers are stage 2's A operand
+// as they stand: register i of lane l holds f0 = 8 (i / 4) + 4 (l / 32) + i % 4
+// and r = l % 32, so K-step t takes registers 8 t .. 8 t + 7 and the constant
+// B operand lists f0 in that order.  Complex products take four real MFMAs
+// (re*re + im*(-im), re*im + im*re); SPLIT keeps hi*hi + hi*lo + lo*hi.
+// One wavefront per image row: |E_k|^2 is accumulated over the kernels in
+// stage 2's register layout, then the I_Q row is moved to the FFT layout
+// through LDS for the forward row DFT to the 2b band (the FP32 epilogue).
+// tab: [3][6][64] operand fragments (stage 1, then stage 2's two K-steps;
+// components re, im, -im, then their low halves); twl: [16][64] twiddles.
+template <typename E, bool SPLIT, int P>
+__global__ __launch_bounds__(256, 2) void k_pass_x_fwd_mfma(const cf *__restrict__ Y, cf *__restrict__ Ib, Geo g,
+                                                        const typename Mfma<E>::V *__restrict__ tab,
+                                                        const cf *__restrict__ twl, const cf *__restrict__ tw_table,
+                                                        float sin, float sout) {
+  constexpr int Q = 32 * P, T = FftPlan<Q>::T, EQ = Q / T, KS2 = P <= 16 ? 1 : 2, NC = SPLIT ? 6 : 3;
+  using V = typename Mfma<E>::V;
+  extern __shared__ cf smem[];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6, m = l & 31, hl = l >> 5;
+  const int y = blockIdx.x * 4 + w, clip = blockIdx.y;
+  // LDS: stage 2's operand fragments and the twiddles (shared by the four
+  // rows of the block, read per use to keep registers for occupancy), then
+  // one exchange region per row
+  V *const lb2 = reinterpret_cast<V *>(smem);
+  cf *const ltw = reinterpret_cast<cf *>(lb2 + KS2 * NC * 64);
+  float *const xch = reinterpret_cast<float *>(ltw + 16 * 64) + w * RowXch<Q>::floats;
+  for (int e = threadIdx.x; e < KS2 * NC * 64; e += 256) {
+    const int t = e / (NC * 64), c = (e / 64) % NC, ll = e % 64;
+    lb2[e] = tab[((1 + t) * 6 + c) * 64 + ll];
+  }
+  for (int e = threadIdx.x; e < 16 * 64; e += 256) ltw[e] = twl[e];
+  __syncthreads();
+  // stage 1's constant operand stays in registers
+  V b1[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) b1[c] = tab[c * 64 + l];
+  // this lane's stage-1 A elements: f0 = m, f1 = 8 hl + j -> f = f0 + P (f1 - 8)
+  const size_t kstride = size_t(g.nt) * Q * kC;
+  const cf *yc = Y + size_t(clip) * g.K * kstride;
+  // f = m + P (8 hl + j - 8) at column f + b: tile (f + b) / 4, slot (f + b) % 4
+  const int f00 = m + P * (8 * hl - 8) + g.b;
+  auto load = [&](cf (&x)[8], int k) {
+    const cf *src = yc + size_t(k) * kstride + size_t(y) * kC;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int col = f00 + P * j;
+      const bool ok = m < P && col >= 0 && col <= 2 * g.b;
+      x[j] = ok ? src[(col >> 2) * (Q * kC) + (col & 3)] : cmake(0.f, 0.f);
+    }
+  };
+  auto to_v = [&](const float (&x)[8], V &hi, V &lo) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const E h = E(x[j]);
+      hi[j] = h;
+      if constexpr (SPLIT) lo[j] = E(x[j] - float(h));
+    }
+  };
+  // (ar + i ai)(br + i bi) accumulated into (dr, di): components 0 re, 1 im, 2 -im (+3 for the low halves)
+  // the real and imaginary chains alternate, so that consecutive MFMAs do
+  // not wait on each other's accumulator
+  auto cmac = [&](const V &arh, const V &arl, const V &aih, const V &ail, const V (&b)[NC], f16v &dr, f16v &di) {
+    dr = Mfma<E>::run(arh, b[0], dr);
+    di = Mfma<E>::run(arh, b[1], di);
+    dr = Mfma<E>::run(aih, b[2], dr);
+    di = Mfma<E>::run(aih, b[0], di);
+    if constexpr (SPLIT) {
+      dr = Mfma<E>::run(arh, b[3], dr);
+      di = Mfma<E>::run(arh, b[4], di);
+      dr = Mfma<E>::run(arl, b[0], dr);
+      di = Mfma<E>::run(arl, b[1], di);
+      dr = Mfma<E>::run(aih, b[5], dr);
+      di = Mfma<E>::run(aih, b[3], di);
+      dr = Mfma<E>::run(ail, b[2], dr);
+      di = Mfma<E>::run(ail, b[0], di);
+    }
+  };
+  float acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int k = 0; k < g.K; ++k) {
+    cf raw[8];
+    load(raw, k);
+    float xr[8], xi[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      xr[j] = raw[j].x * sin;
+      xi[j] = raw[j].y * sin;
+    }
+    V arh, arl, aih, ail;
+    to_v(xr, arh, arl);
+    to_v(xi, aih, ail);
+    f16v d1r = f16v{}, d1i = f16v{};
+    cmac(arh, arl, aih, ail, b1, d1r, d1i);
+    // twiddle w^(f0 r), FP32
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const cf tw = ltw[i * 64 + l];
+      const float re = d1r[i] * tw.x - d1i[i] * tw.y;
+      const float im = d1r[i] * tw.y + d1i[i] * tw.x;
+      d1r[i] = re;
+      d1i[i] = im;
+    }
+    f16v d2r = f16v{}, d2i = f16v{};
+#pragma unroll
+    for (int t = 0; t < KS2; ++t) {
+      float pr[8], pi[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        pr[j] = d1r[8 * t + j];
+        pi[j] = d1i[8 * t + j];
+      }
+      V prh, prl, pih, pil;
+      to_v(pr, prh, prl);
+      to_v(pi, pih, pil);
+      V b2[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) b2[c] = lb2[(t * NC + c) * 64 + l];
+      cmac(prh, prl, pih, pil, b2, d2r, d2i);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] += d2r[i] * d2r[i] + d2i[i] * d2i[i];
+  }
+  // I_Q row to the FFT layout: register i of lane l is position q = r + 32 s,
+  // r = 8 (i / 4) + 4 hl + i % 4, s = m (s < P)
+  if (m < P) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) xch[8 * (i >> 2) + 4 * hl + (i & 3) + 32 * m] = acc[i] * sout;
+  }
+  xsync<64>();
+  // every lane of the wavefront takes part in the row transform; lanes with
+  // the same t hold the same values
+  const int t = l % T;
+  cf v[EQ];
+#pragma unroll
+  for (int i = 0; i < EQ; ++i) v[i] = cmake(xch[t + T * i], 0.f);
+  xsync<64>();
+  row_fft<Q, -1>(v, xch, t, tw_table);
+  if (l < T)
+    store_band_row_v<Q, T>(v, Ib + size_t(clip) * g.ntD * size_t(Q) * kC, unsigned(size_t(g.Dp) * Q * sizeof(cf)),
+                           y, t, 2 * g.b, g.Dp, g.dose / (float(Q) * float(Q)));
+}
+
+
 // ------------------------------------------------------------ loss reduction
 __global__ __launch_bounds__(256) void k_loss_reduce(const double *__restrict__ part, int n_per_clip,
                                                      double *__restrict__ loss) {
@@ -1613,6 +1765,38 @@ int pass_x_fwd_q(const cf *Y, const EpiPtrs &ep, cf *Ib, const PassGeo &pg, cons
   if (pr) LITHO_PX_FWD(1, true);
   LITHO_PX_FWD(1, false);
 #undef LITHO_PX_FWD
+}
+
+template <typename E, bool SPLIT, int P>
+int pass_x_fwd_mfma_p(const cf *Y, cf *Ib, const PassGeo &pg, const void *tab, const cf *twl, const cf *twQ,
+                      float sin, int nclips, hipStream_t s) {
+  constexpr int Q = 32 * P;
+  Geo g = to_geo(pg);
+  using Vt = typename dev::Mfma<E>::V;
+  constexpr int KS2 = P <= 16 ? 1 : 2, NC = SPLIT ? 6 : 3;
+  const size_t sh = size_t(KS2) * NC * 64 * sizeof(Vt) + 16 * 64 * sizeof(cf) +
+                    size_t(4) * dev::RowXch<Q>::floats * sizeof(float);
+  const dim3 grid(Q / 4, nclips);
+  const float sout = 1.0f / (sin * sin);
+  return launch("pass_x_fwd_mfma", KPTR(dev::k_pass_x_fwd_mfma<E, SPLIT, P>), grid, sh, s, [&] {
+    hipLaunchKernelGGL((dev::k_pass_x_fwd_mfma<E, SPLIT, P>), grid, dim3(256), sh, s, Y, Ib, g,
+                       static_cast<const Vt *>(tab), twl, twQ, sin, sout);
+  });
+}
+template <typename E, bool SPLIT>
+int pass_x_fwd_mfma_e(const cf *Y, cf *Ib, const PassGeo &pg, const void *tab, const cf *twl, const cf *twQ,
+                      float sin, int nclips, hipStream_t s) {
+  switch (pg.Q / 32) {
+#define LITHO_XM(P) \
+  case P:           \
+    return pass_x_fwd_mfma_p<E, SPLIT, P>(Y, Ib, pg, tab, twl, twQ, sin, nclips, s);
+    LITHO_XM(2) LITHO_XM(3) LITHO_XM(4) LITHO_XM(5) LITHO_XM(6) LITHO_XM(8) LITHO_XM(10) LITHO_XM(12)
+    LITHO_XM(16) LITHO_XM(20) LITHO_XM(24) LITHO_XM(32)
+#undef LITHO_XM
+    default:
+      set_error("no two-stage row transform for inner grid %d", pg.Q);
+      return LITHO_E_UNSUPPORTED;
+  }
 }
 
 template <int Q>
@@ -1866,6 +2050,25 @@ int run_pass_x_fwd(const cf2 *Y, const EpiPtrs &ep, cf2 *Ib, const PassGeo &pg, 
                    hipStream_t s) {
   LITHO_DISPATCH_Q(pg.Q, (pass_x_fwd_q<NN>((const cf *)Y, ep, (cf *)Ib, pg, (const cf *)twQ, nclips, s)));
 }
+int run_pass_x_fwd_mfma(const cf2 *Y, cf2 *Ib, const PassGeo &g, const void *tab, const cf2 *twl, const cf2 *twQ,
+                        int prec, int nclips, hipStream_t s) {
+  if (!row_mfma_ok(g.Q, g.N)) {
+    set_error("no two-stage row transform for inner grid %d of a %d grid", g.Q, g.N);
+    return LITHO_E_UNSUPPORTED;
+  }
+  const bool split = prec == LITHO_PREC_F16X3 || prec == LITHO_PREC_BF16X3;
+  const bool bf = prec == LITHO_PREC_BF16X3 || prec == LITHO_PREC_BF16;
+  // the band rows are at most ~0.05 in magnitude: FP16 operands are scaled by
+  // 2^12 so that the low halves stay normal; the image is scaled back by 2^-24
+  const cf *y = (const cf *)Y, *tl = (const cf *)twl, *tq = (const cf *)twQ;
+  cf *ib = (cf *)Ib;
+  if (bf) {
+    if (split) return pass_x_fwd_mfma_e<__bf16, true>(y, ib, g, tab, tl, tq, 1.0f, nclips, s);
+    return pass_x_fwd_mfma_e<__bf16, false>(y, ib, g, tab, tl, tq, 1.0f, nclips, s);
+  }
+  if (split) return pass_x_fwd_mfma_e<_Float16, true>(y, ib, g, tab, tl, tq, 4096.0f, nclips, s);
+  return pass_x_fwd_mfma_e<_Float16, false>(y, ib, g, tab, tl, tq, 4096.0f, nclips, s);
+}
 int run_pass_x_adj(cf2 *Y, const float *G, size_t g_clip_stride, const cf2 *Gband, const PassGeo &pg,
                    const cf2 *twQ, int nclips, hipStream_t s) {
   LITHO_DISPATCH_Q(pg.Q, (pass_x_adj_q<NN>((cf *)Y, G, g_clip_stride, (const cf *)Gband, pg, (const cf *)twQ,
@@ -1917,11 +2120,73 @@ void fill_adj_table(int Q, int b, bool bf16, std::vector<uint16_t> &out) {
     fill_adj_table_e<_Float16>(Q, b, out);
 }
 
+template <typename E>
+void fill_row_mfma_table_e(int Q, std::vector<uint16_t> &tab, std::vector<float2> &twl) {
+  const int P = Q / 32;
+  auto put = [&](int part, int c, int l, int j, double v) {
+    const E h = E(float(v));
+    const E lo = E(float(v - double(float(h))));
+    uint16_t bits;
+    std::memcpy(&bits, &h, 2);
+    tab[((size_t(part) * 6 + c) * 64 + l) * 8 + j] = bits;
+    std::memcpy(&bits, &lo, 2);
+    tab[((size_t(part) * 6 + c + 3) * 64 + l) * 8 + j] = bits;
+  };
+  auto put_c = [&](int part, int l, int j, double re, double im) {
+    put(part, 0, l, j, re);
+    put(part, 1, l, j, im);
+    put(part, 2, l, j, -im);
+  };
+  tab.assign(size_t(3) * 6 * 64 * 8, 0);
+  for (int l = 0; l < 64; ++l)
+    for (int j = 0; j < 8; ++j) {
+      const int hl = l >> 5, m = l & 31;
+      // stage 1: B[f1 = 8 hl + j][r = m] = exp(2 pi i (f1 - 8) r / 32)
+      {
+        const double a = 2.0 * M_PI * double(((8 * hl + j - 8) * m) % 32) / 32.0;
+        put_c(0, l, j, std::cos(a), std::sin(a));
+      }
+      // stage 2, K-step t: B[k = 8 hl + j][s = m] = exp(2 pi i f0 s / P) with f0 the
+      // row of stage 1's accumulator register 8 t + j in a lane of this half
+      for (int t = 0; t < 2; ++t) {
+        const int f0 = 16 * t + 8 * (j >> 2) + 4 * hl + (j & 3), sidx = m;
+        double re = 0, im = 0;
+        if (f0 < P && sidx < P) {
+          const double a = 2.0 * M_PI * double((f0 * sidx) % P) / double(P);
+          re = std::cos(a);
+          im = std::sin(a);
+        }
+        put_c(1 + t, l, j, re, im);
+      }
+    }
+  // twiddles w^(f0 r), w = exp(2 pi i / Q), for register i of lane l
+  twl.assign(size_t(16) * 64, make_float2(0.f, 0.f));
+  for (int i = 0; i < 16; ++i)
+    for (int l = 0; l < 64; ++l) {
+      const int f0 = 8 * (i >> 2) + 4 * (l >> 5) + (i & 3), r = l & 31;
+      if (f0 >= P) continue;
+      const double a = 2.0 * M_PI * double((f0 * r) % Q) / double(Q);
+      twl[size_t(i) * 64 + l] = make_float2(float(std::cos(a)), float(std::sin(a)));
+    }
+}
+
 void fill_band_table(int Q, int b, bool bf16, std::vector<uint16_t> &out) {
   if (bf16)
     fill_band_table_e<__bf16>(Q, b, out);
   else
     fill_band_table_e<_Float16>(Q, b, out);
+}
+
+bool row_mfma_ok(int Q, int N) {
+  // the inner grids 32 P (P <= 32) of the resampled route
+  return Q < N && Q % 32 == 0 && Q / 32 <= 32 && pass_threads(Q) > 0;
+}
+
+void fill_row_mfma_table(int Q, bool bf16, std::vector<uint16_t> &tab, std::vector<float2> &twl) {
+  if (bf16)
+    fill_row_mfma_table_e<__bf16>(Q, tab, twl);
+  else
+    fill_row_mfma_table_e<_Float16>(Q, tab, twl);
 }
 
 int twiddle_table(int L, std::vector<float2> &out) {

@@ -75,6 +75,14 @@ int run_grad_cols(const double2 *part, int nparts, cf2 *tmp, const PassGeo &g, c
 int run_loss_reduce(const double *part, int n_per_clip, double *loss, int nclips, hipStream_t s);
 
 // Split-precision band DFT-GEMM form of the forward column pass (matrix cores).
+// Forward row pass of the resampled route as two dense DFT stages on the
+// matrix cores (split-precision modes; inner grids Q = 32 P, P <= 32, Q < N):
+// I_Q rows accumulated from Y_k and their row DFT to the 2b band, as
+// run_pass_x_fwd's band output.  tab / twl from fill_row_mfma_table.
+bool row_mfma_ok(int Q, int N);
+void fill_row_mfma_table(int Q, bool bf16, std::vector<uint16_t> &tab, std::vector<float2> &twl);
+int run_pass_x_fwd_mfma(const cf2 *Y, cf2 *Ib, const PassGeo &g, const void *tab, const cf2 *twl, const cf2 *twQ,
+                        int prec, int nclips, hipStream_t s);
 int run_pass_y_fwd_mfma(const cf2 *bank, const cf2 *Mh, cf2 *Y, const PassGeo &g, const void *tab, int prec,
                         int nclips, hipStream_t s);
 // B-operand table of that GEMM for inner grid Q and band half-width b (FP16 or BF16 bits).

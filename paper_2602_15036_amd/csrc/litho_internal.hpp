@@ -26,6 +26,7 @@ struct CallLayout {
   PassGeo g;
   int nblk = 0;    // row-pass blocks per clip and plane (loss partials)
   bool resample = false;  // image carried through the 4b+1 intensity band (Q < N, or a resist blur)
+  bool row_mfma = false;  // split modes: two-stage MFMA forward row pass, FP32 column passes
   int pp = 1;      // focus planes run concurrently (each with its own Y, G and band buffers)
   size_t b_S1 = 0, b_Mh = 0, b_Y = 0, b_G = 0, b_part = 0, b_loss = 0, b_X = 0;
   size_t per_clip = 0;
@@ -56,6 +57,9 @@ struct litho_bank {
   float2 *d_twQ = nullptr;   // exp(-2 pi i e / Q)
   // band DFT-GEMM tables for Q, built on first use: [forward FP16, forward BF16, adjoint FP16, adjoint BF16]
   void *d_gemm[4] = {nullptr, nullptr, nullptr, nullptr};
+  // two-stage row transform operands for Q, built on first use: [FP16, BF16], and its twiddles
+  void *d_rowmma[2] = {nullptr, nullptr};
+  float2 *d_rowtw = nullptr;
   std::mutex mu;
   std::map<hipStream_t, litho::Workspace> ws;
   // second per-stream workspace for calls that hold buffers across an imaging call

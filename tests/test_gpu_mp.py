@@ -1,13 +1,17 @@
-"""Split-precision band DFT-GEMM modes against the FP64 oracle (through the C ABI).
+"""Split-precision modes against the FP64 oracle (through the C ABI).
 
-Each mode's relative L2 error of the image and the gradient is printed (run
-with -s to see the table).  The gates sit at about three times the largest
-error measured for the mode over these tests (128-4096 clips, 1-3 planes),
-so that an accuracy regression of a few times fails:
+Inner grids 32 P <= 1024 of the resampled route (here 96, 160, 320 and the
+1024^2 bench batch's 640) run the forward row pass as two MFMA DFT stages
+with FP32 column passes; the others (Q = N, and the 4096^2 tile's 2560) run
+the column passes as band DFT-GEMMs.  Each mode's relative L2 error of the
+image and the gradient is printed (run with -s to see the table).  The gates
+sit at about three times the largest error measured for the mode over these
+tests (128-4096 clips, 1-3 planes, both placements), so that an accuracy
+regression of a few times fails:
   f16x3:  image 5.7e-7, gradient 1.1e-6 measured (FP32 level: hi*hi + hi*lo + lo*hi of 11-bit halves);
-  bf16x3: image 4.8e-6, gradient 9.1e-6 measured (~2^-16 per product);
-  f16:    image 3.8e-4, gradient 7.3e-4 measured (one 11-bit term);
-  bf16:   image 2.8e-3, gradient 5.6e-3 measured (one 8-bit term).
+  bf16x3: image 5.3e-6, gradient 9.2e-6 measured (~2^-16 per product);
+  f16:    image 4.1e-4, gradient 7.4e-4 measured (one 11-bit term);
+  bf16:   image 3.3e-3, gradient 6.0e-3 measured (one 8-bit term).
 FP32 keeps the path's own gates (image 1e-5, gradient 1e-4).
 """
 import os
