@@ -63,16 +63,21 @@ enum {
  * one. */
 enum { LITHO_SRC_ANNULAR = 0, LITHO_SRC_DIPOLE_X = 1, LITHO_SRC_DIPOLE_Y = 2, LITHO_SRC_POINTS = 3 };
 
-/* Arithmetic of the band DFT stages (the column transforms between the
- * cropped pupil band and the inner grid; north of those every pass stays FP32,
- * and loss and gradient reductions stay FP64).
+/* Arithmetic of the DFT stages that run on the matrix cores (every other
+ * pass stays FP32, and loss and gradient reductions stay FP64).
  *   FP32:        FFT passes in FP32.
- *   F16X3/BF16X3: the band transforms as dense DFT-GEMMs on the matrix cores,
- *                FP16 / BF16 operands split into hi + lo halves, products
- *                hi*hi + hi*lo + lo*hi, FP32 accumulation.  Near-FP32 (F16X3)
- *                or ~1e-5 relative (BF16X3) accuracy.
- *   F16/BF16:    the same GEMMs with one FP16 / BF16 term (hi*hi only);
- *                ~1e-3 relative accuracy, reported as a reference point. */
+ *   F16X3/BF16X3: dense DFT stages on the matrix cores, FP16 / BF16 operands
+ *                split into hi + lo halves, products hi*hi + hi*lo + lo*hi,
+ *                FP32 accumulation.  On inner grids 32 P <= 1024 of the
+ *                resampled route the band-limited inverse row transform of
+ *                the forward pass runs as two such stages (a 16 -> 32 DFT
+ *                and a P-point DFT around an FP32 twiddle) and the column
+ *                passes stay FP32; on the other inner grids the column
+ *                transforms between the pupil band and the inner grid run as
+ *                band DFT-GEMMs.  Near-FP32 (F16X3) or ~1e-5 relative
+ *                (BF16X3) accuracy.
+ *   F16/BF16:    the same stages with one FP16 / BF16 term (hi*hi only);
+ *                ~1e-3 relative accuracy. */
 enum { LITHO_PREC_FP32 = 0, LITHO_PREC_F16X3 = 1, LITHO_PREC_BF16X3 = 2, LITHO_PREC_F16 = 3, LITHO_PREC_BF16 = 4 };
 
 /* Optical settings of one bank (Sec. III-A, Eqs. 1-2).  All lengths in nm.
