@@ -11,8 +11,9 @@
 // layout the last pass writes exactly the positions its thread holds, so a
 // transform of P passes needs P - 1 LDS exchanges.
 //
-// Twiddles come from a table tw[e] = exp(-2 pi i e / L) computed on the host in
-// FP64 and rounded once to FP32 (no device sin/cos, no recurrences).  The
+// Twiddles come from per-pass tables computed on the host in FP64 and rounded
+// once to FP32 (no device sin/cos, no recurrences); radix-4 passes hold them
+// as (cosine, tangent) pairs for a fused multiply-add butterfly.  The
 // small in-register DFTs use exact radix-2/4 forms, radix-3/5 forms with
 // FP64-rounded constants, Good-Thomas splits for coprime composites and a
 // Cooley-Tukey split with constant twiddles for 8 and 16.
@@ -387,9 +388,11 @@ template <int L>
 constexpr int lds_len_half() { return L + pad_max(typename HalfPlan<L>::M{}) * (L / 32) + HalfPlan<L>::extra; }
 
 // Twiddle table layout.  Pass p (radix R after radices multiplying to S > 1)
-// owns S * (R - 1) consecutive entries starting at tw_offset<p>; entry
-// [k][r - 1] = exp(-2 pi i k r / (S R)).  A butterfly therefore reads its
-// R - 1 twiddles from one base address.
+// owns S * tw_per(R, S) consecutive entries; a butterfly reads its twiddles
+// from one base address.  Radix 4: entries [k][0] = (cos a, tan a) and
+// [k][1] = (cos 2a, tan 2a), a = -2 pi k / (4 S) (the form of dft4_tw below);
+// other radices: entry [k][r - 1] = exp(-2 pi i k r / (S R)).
+constexpr int tw_per(int R, int S) { return S > 1 ? (R == 4 ? 2 : R - 1) : 0; }
 template <int S, int... Rs>
 struct TwSize;
 template <int S>
@@ -398,7 +401,7 @@ struct TwSize<S> {
 };
 template <int S, int R, int... Rest>
 struct TwSize<S, R, Rest...> {
-  static constexpr int value = (S > 1 ? S * (R - 1) : 0) + TwSize<S * R, Rest...>::value;
+  static constexpr int value = S * tw_per(R, S) + TwSize<S * R, Rest...>::value;
 };
 template <int L, typename Rad>
 struct TwTable;
@@ -439,6 +442,59 @@ __device__ __forceinline__ int opaque_lane(int x) {
   return x;
 }
 
+// Radix-4 butterfly of a Stockham pass with its input twiddles w, w^2, w^3
+// (inputs u[r] scaled by w^r, then the 4-point DFT), factored as in Linzer
+// and Feig's FFT for fused multiply-add units: w^2 on the pairs (u0, u2) and
+// (u1, u3), then w on the odd half, each product written c (x - t y, y + t x)
+// with the cosine c folded into the butterfly's fused multiply-adds.  24 FMAs
+// against 12 for three complex products plus 16 additions.  w1 = (cos a,
+// tan a), w2 = (cos 2a, tan 2a), the tangents already signed for DIR; the
+// table clamps |cos| to at least 2^-26, where the represented twiddle is
+// off by less than half an FP32 ulp of 1.
+template <int DIR>
+__device__ __forceinline__ void dft4_tw(cf *u, cf w1, cf w2) {
+  const float p2x = fmaf(-w2.y, u[2].y, u[2].x), p2y = fmaf(w2.y, u[2].x, u[2].y);
+  const float p3x = fmaf(-w2.y, u[3].y, u[3].x), p3y = fmaf(w2.y, u[3].x, u[3].y);
+  const cf a = cmake(fmaf(w2.x, p2x, u[0].x), fmaf(w2.x, p2y, u[0].y));
+  const cf b = cmake(fmaf(-w2.x, p2x, u[0].x), fmaf(-w2.x, p2y, u[0].y));
+  const cf e = cmake(fmaf(w2.x, p3x, u[1].x), fmaf(w2.x, p3y, u[1].y));
+  const cf f = cmake(fmaf(-w2.x, p3x, u[1].x), fmaf(-w2.x, p3y, u[1].y));
+  const float ex = fmaf(-w1.y, e.y, e.x), ey = fmaf(w1.y, e.x, e.y);
+  const float fx = fmaf(-w1.y, f.y, f.x), fy = fmaf(w1.y, f.x, f.y);
+  u[0] = cmake(fmaf(w1.x, ex, a.x), fmaf(w1.x, ey, a.y));
+  u[2] = cmake(fmaf(-w1.x, ex, a.x), fmaf(-w1.x, ey, a.y));
+  // DIR i w f = DIR (-c fy, c fx)
+  constexpr float sg = DIR > 0 ? 1.f : -1.f;
+  u[1] = cmake(fmaf(-sg * w1.x, fy, b.x), fmaf(sg * w1.x, fx, b.y));
+  u[3] = cmake(fmaf(sg * w1.x, fy, b.x), fmaf(-sg * w1.x, fx, b.y));
+}
+
+// Input twiddles of butterfly j of a pass (radix R after radices multiplying
+// to S, its table entries from OFF), then its R-point DFT, in place.
+template <int R, int S, int OFF, int DIR>
+__device__ __forceinline__ void twiddled_dft(cf (&u)[R], const cf *__restrict__ twp, int j) {
+  if constexpr (S > 1 && R == 4) {
+    const cf *tb = twp + OFF + (j % S) * 2;
+    cf w1 = tb[0], w2 = tb[1];
+    if constexpr (DIR > 0) {
+      w1.y = -w1.y;
+      w2.y = -w2.y;
+    }
+    dft4_tw<DIR>(u, w1, w2);
+  } else {
+    if constexpr (S > 1) {
+      const cf *tb = twp + OFF + (j % S) * (R - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cf w = tb[r - 1];
+        if constexpr (DIR > 0) w.y = -w.y;
+        u[r] = cmul(u[r], w);
+      }
+    }
+    Dft<R, DIR>::run(u);
+  }
+}
+
 // One Stockham pass of radix R after passes whose radices multiply to S;
 // its twiddles start at entry OFF of the table; its exchange pads by M.
 template <int L, int T, int DIR, int R, int S, int OFF, bool LAST, int M>
@@ -454,16 +510,7 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[L / T], cf *__restrict__ b
     cf u[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[mb + r * NB];
-    if constexpr (S > 1) {
-      const cf *tb = twp + OFF + (j % S) * (R - 1);
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cf w = tb[r - 1];
-        if constexpr (DIR > 0) w.y = -w.y;
-        u[r] = cmul(u[r], w);
-      }
-    }
-    Dft<R, DIR>::run(u);
+    twiddled_dft<R, S, OFF, DIR>(u, twp, j);
     if constexpr (LAST) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[mb + r * NB] = u[r];
@@ -506,16 +553,7 @@ __device__ __forceinline__ void stockham_pass_half(cf (&v)[L / T], float *__rest
     cf u[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[mb + r * NB];
-    if constexpr (S > 1) {
-      const cf *tb = twp + OFF + (j % S) * (R - 1);
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cf w = tb[r - 1];
-        if constexpr (DIR > 0) w.y = -w.y;
-        u[r] = cmul(u[r], w);
-      }
-    }
-    Dft<R, DIR>::run(u);
+    twiddled_dft<R, S, OFF, DIR>(u, twp, j);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[mb + r * NB] = u[r];
   }
@@ -548,7 +586,7 @@ __device__ __forceinline__ void run_passes_half(cf (&v)[L / T], float *buf, int 
   stockham_pass_half<L, T, DIR, R, S, OFF, sizeof...(Rest) == 0, PadAt<P, typename HalfPlan<L>::M>::value>(
       v, buf, t, tw);
   if constexpr (sizeof...(Rest) > 0)
-    run_passes_half<L, T, DIR, S * R, OFF + (S > 1 ? S * (R - 1) : 0), P + 1, Rest...>(v, buf, t, tw);
+    run_passes_half<L, T, DIR, S * R, OFF + S * tw_per(R, S), P + 1, Rest...>(v, buf, t, tw);
 }
 
 template <int L, int DIR, int... Rs>
@@ -562,7 +600,7 @@ __device__ __forceinline__ void run_passes(cf (&v)[L / T], cf *buf, int t, const
   stockham_pass<L, T, DIR, R, S, OFF, sizeof...(Rest) == 0, PadAt<P, typename PadPlan<L>::M>::value>(v, buf, t,
                                                                                                      tw);
   if constexpr (sizeof...(Rest) > 0)
-    run_passes<L, T, DIR, S * R, OFF + (S > 1 ? S * (R - 1) : 0), P + 1, Rest...>(v, buf, t, tw);
+    run_passes<L, T, DIR, S * R, OFF + S * tw_per(R, S), P + 1, Rest...>(v, buf, t, tw);
 }
 
 template <int L, int DIR, int... Rs>
@@ -581,14 +619,22 @@ struct TwFill<S> {
 template <int S, int R, int... Rest>
 struct TwFill<S, R, Rest...> {
   static void run(float2 *out, int off) {
-    if (S > 1) {
+    if (S > 1 && R == 4) {
+      for (int k = 0; k < S; ++k)
+        for (int m = 1; m <= 2; ++m) {
+          const double a = -2.0 * 3.14159265358979323846 * double(k) * double(m) / double(S * R);
+          double c = __builtin_cos(a);
+          if (__builtin_fabs(c) < 0x1p-26) c = 0x1p-26;
+          out[off + k * 2 + (m - 1)] = make_float2(float(c), float(__builtin_sin(a) / c));
+        }
+    } else if (S > 1) {
       for (int k = 0; k < S; ++k)
         for (int r = 1; r < R; ++r) {
           const double a = -2.0 * 3.14159265358979323846 * double(k) * double(r) / double(S * R);
           out[off + k * (R - 1) + (r - 1)] = make_float2(float(__builtin_cos(a)), float(__builtin_sin(a)));
         }
     }
-    TwFill<S * R, Rest...>::run(out, off + (S > 1 ? S * (R - 1) : 0));
+    TwFill<S * R, Rest...>::run(out, off + S * tw_per(R, S));
   }
 };
 template <int L, int... Rs>
