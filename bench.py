@@ -92,6 +92,8 @@ def launch_bytes(name, g, c):
         return K * 8 * B * B + c * (8 * B * B + K * 8 * Q * B)
     if name == "pass_x_fwd":
         return c * (K * 8 * Q * B + (8 * Q * D if resample else 12 * N * N))
+    if name in ("up_cols", "down_cols"):  # both resampling column transforms in one pass
+        return c * 8 * D * (Q + N)
     if name == "up_cols_q":
         return c * 8 * D * (Q + D)
     if name == "up_cols_n":

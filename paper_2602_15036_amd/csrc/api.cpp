@@ -579,6 +579,11 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
     auto *G = reinterpret_cast<float *>(q); q += L.b_G * n;
     auto *X1 = reinterpret_cast<float2 *>(q); q += L.b_X * n;
     auto *X2 = reinterpret_cast<float2 *>(q);
+    // the N-row band of the image and of the residual: X2 when one pass does
+    // both resampling column transforms (its input and output cannot share a
+    // buffer), X1 otherwise
+    const bool fuse_cols = resample && col_resample_ok(g.Q, g.N);
+    float2 *const XN = fuse_cols ? X2 : X1;
     const hipStream_t s = slot == 0 ? s_main : side[slot - 1];
     EpiPtrs ep;
     ep.image = image;
@@ -598,14 +603,18 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
         LITHO_TRY(run_pass_x_fwd_mfma(Y, X1, g, row_tab, row_tw, twQ, prec, n, s));
       else
         LITHO_TRY(run_pass_x_fwd(Y, EpiPtrs{}, X1, g, twQ, n, s));
-      LITHO_TRY(run_col_fft("up_cols_q", g.Q, -1, X1, X2, g.ntD, -1, h2, twQ, 1.0f, n, s));
       // resist kernel of Eq. 5 on the intensity band: R = I (x) K_resist
-      LITHO_TRY(run_band_gauss(X2, h2, g.ntD, double(g.N), blur, band_clip, n, s));
-      LITHO_TRY(run_col_fft("up_cols_n", g.N, +1, X2, X1, g.ntD, h2, -1, twN, 1.0f, n, s));
-      if (grad && fused)  // image, loss and the residual's row DFT to the band, in place in X1
-        LITHO_TRY(run_rows_image_residual("image_residual_rows", g.N, X1, h2, g.Dp, ep, g, twN, 1.0f, n, s));
+      if (fuse_cols) {
+        LITHO_TRY(run_col_resample("up_cols", g.Q, g.N, true, X1, XN, g.ntD, h2, twQ, twN, 1.0f, blur, n, s));
+      } else {
+        LITHO_TRY(run_col_fft("up_cols_q", g.Q, -1, X1, X2, g.ntD, -1, h2, twQ, 1.0f, n, s));
+        LITHO_TRY(run_band_gauss(X2, h2, g.ntD, double(g.N), blur, band_clip, n, s));
+        LITHO_TRY(run_col_fft("up_cols_n", g.N, +1, X2, XN, g.ntD, h2, -1, twN, 1.0f, n, s));
+      }
+      if (grad && fused)  // image, loss and the residual's row DFT to the band, in place
+        LITHO_TRY(run_rows_image_residual("image_residual_rows", g.N, XN, h2, g.Dp, ep, g, twN, 1.0f, n, s));
       else if (ep.image || ep.target)
-        LITHO_TRY(run_rows_inv_real("up_rows", g.N, X1, h2, g.Dp, nullptr, ep, g, twN, 1.0f, n, s));
+        LITHO_TRY(run_rows_inv_real("up_rows", g.N, XN, h2, g.Dp, nullptr, ep, g, twN, 1.0f, n, s));
     }
     if (!grad) continue;
     const float *Gp = fused ? G : grad_image + size_t(pl) * NN;
@@ -615,12 +624,16 @@ int run_chunk(litho_bank *bk, const CallLayout &L, char *ws, const float *mask, 
     } else {
       // G low-passed to |f| <= 2b and sampled on the Q grid (scaled by 1/Q^2);
       // the fused step's row DFT of G was done by the image row pass
-      if (!fused) LITHO_TRY(run_rows_fwd_real("down_rows", g.N, Gp, gstride, X1, h2, g.Dp, twN, 1.0f, n, s));
-      LITHO_TRY(run_col_fft("down_cols_n", g.N, -1, X1, X2, g.ntD, -1, h2, twN, 1.0f, n, s));
+      if (!fused) LITHO_TRY(run_rows_fwd_real("down_rows", g.N, Gp, gstride, XN, h2, g.Dp, twN, 1.0f, n, s));
       // dL/dI = K_resist (x) dL/dR (the Gaussian is symmetric)
-      LITHO_TRY(run_band_gauss(X2, h2, g.ntD, double(g.N), blur, band_clip, n, s));
-      LITHO_TRY(run_col_fft("down_cols_q", g.Q, +1, X2, X1, g.ntD, h2, -1, twQ,
-                            float(1.0 / (double(g.Q) * double(g.Q))), n, s));
+      const float qscale = float(1.0 / (double(g.Q) * double(g.Q)));
+      if (fuse_cols) {
+        LITHO_TRY(run_col_resample("down_cols", g.Q, g.N, false, XN, X1, g.ntD, h2, twQ, twN, qscale, blur, n, s));
+      } else {
+        LITHO_TRY(run_col_fft("down_cols_n", g.N, -1, XN, X2, g.ntD, -1, h2, twN, 1.0f, n, s));
+        LITHO_TRY(run_band_gauss(X2, h2, g.ntD, double(g.N), blur, band_clip, n, s));
+        LITHO_TRY(run_col_fft("down_cols_q", g.Q, +1, X2, X1, g.ntD, h2, -1, twQ, qscale, n, s));
+      }
       LITHO_TRY(run_pass_x_adj(Y, nullptr, 0, X1, g, twQ, n, s));
     }
     if (prec == LITHO_PREC_FP32 || L.row_mfma)

@@ -646,6 +646,102 @@ __global__ __launch_bounds__(ColBlock<L>::threads) void k_col_fft(const cf *__re
   }
 }
 
+// ------------------------------------------------------------ resampling column pass
+// Both column transforms of a band resampling in one pass: for each tile
+// column, a length-LA DFT (DIRA) of all LA rows, the band |f| <= h kept (and,
+// with gc > 0, scaled by the Gaussian exp(-gc (kx^2 + ky^2)) of the resist
+// blur), then a length-LB DFT (DIRB) of that band zero-padded to LB rows, all
+// LB rows stored and scaled.  One tile per workgroup; the band crosses between
+// the transforms in LDS, so the D x D band never goes to HBM.  Used both ways
+// between the inner grid Q and the clip grid N (intensity up, residual down).
+template <int LA, int LB>
+struct Resample {
+  static constexpr int TA = FftPlan<LA>::T, TB = FftPlan<LB>::T;
+  static constexpr int threads = 4 * (TA > TB ? TA : TB);
+  static constexpr bool HA = HalfPlan<LA>::ok, HB = HalfPlan<LB>::ok;
+  // band rows of one column in LDS (at most min(LA, LB)), plus a pad slot
+  static constexpr int stage = (LA < LB ? LA : LB) + 2;
+  static constexpr size_t bytes_a = size_t(4) * Xch<LA, HA>::floats * sizeof(float);
+  static constexpr size_t bytes_b = size_t(4) * Xch<LB, HB>::floats * sizeof(float);
+  static constexpr size_t bytes_s = size_t(4) * stage * sizeof(cf);
+  static constexpr size_t bytes_o = size_t(LB) * kC * sizeof(cf);
+  static constexpr size_t m1 = bytes_a > bytes_b ? bytes_a : bytes_b, m2 = bytes_s > bytes_o ? bytes_s : bytes_o;
+  static constexpr size_t bytes = m1 > m2 ? m1 : m2;
+  // each transform's threads fill whole wavefronts (its exchanges synchronise
+  // one wavefront)
+  static_assert((4 * TA) % 64 == 0 && (4 * TB) % 64 == 0, "transforms must fill whole wavefronts");
+};
+template <int LA, int DIRA, int LB, int DIRB>
+__global__ __launch_bounds__((Resample<LA, LB>::threads)) void k_col_resample(const cf *__restrict__ in,
+                                                                            cf *__restrict__ out, int h,
+                                                                            size_t in_clip, size_t out_clip,
+                                                                            const cf *__restrict__ twA,
+                                                                            const cf *__restrict__ twB, float scale,
+                                                                            float gc) {
+  using RS = Resample<LA, LB>;
+  constexpr int TA = RS::TA, TB = RS::TB, EA = LA / TA, EB = LB / TB;
+  extern __shared__ cf smem[];
+  float *const lds = reinterpret_cast<float *>(smem);
+  cf *const stage = smem;  // [4][RS::stage], aliases the exchange regions
+  const int jt = blockIdx.x, clip = blockIdx.y, nt = gridDim.x;
+  // first transform: all LA rows in, the band kept in registers
+  {
+    const int col = threadIdx.x / TA, t = threadIdx.x % TA;
+    cf v[EA];
+    if (col < 4) {
+      const auto src = buf_view(in + clip * in_clip, unsigned(size_t(nt) * LA * kC * sizeof(cf)));
+      const unsigned in0 = unsigned((jt * LA + t) * kC + col) * unsigned(sizeof(cf));
+#pragma unroll
+      for (int i = 0; i < EA; ++i) v[i] = buf_load(src, in0 + unsigned(TA * i * kC * sizeof(cf)));
+      xch_fft<LA, RS::HA, DIRA>(v, lds + col * Xch<LA, RS::HA>::floats, t, twA);
+    }
+    __syncthreads();
+    if (col < 4) {
+      const int kx = jt * kC + col - h;
+#pragma unroll
+      for (int i = 0; i < EA; ++i) {
+        const int r = band_row_of(t + TA * i, LA, h);
+        if (r < 0) continue;
+        cf x = v[i];
+        if (gc > 0.f) x = kx <= h ? cscale(x, expf(-gc * float(kx * kx + (r - h) * (r - h)))) : cmake(0.f, 0.f);
+        stage[col * RS::stage + r] = x;
+      }
+    }
+  }
+  __syncthreads();
+  // second transform: the band zero-padded to LB rows, all LB rows out
+  const int col = threadIdx.x / TB, t = threadIdx.x % TB;
+  cf v[EB];
+  if (col < 4) {
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int r = band_row_of(t + TB * i, LB, h);
+      v[i] = r >= 0 ? stage[col * RS::stage + r] : cmake(0.f, 0.f);
+    }
+  }
+  __syncthreads();
+  if (col < 4) xch_fft<LB, RS::HB, DIRB>(v, lds + col * Xch<LB, RS::HB>::floats, t, twB);
+  // the tile's LB rows of 4 columns cross the LDS once more, so that every
+  // wavefront stores whole 32-byte rows (512 contiguous bytes per store);
+  // column c of row r sits in slot c ^ ((r >> 3) & 3) of the row, which keeps
+  // both the column-wise writes and the row-wise reads free of bank conflicts
+  __syncthreads();
+  if (col < 4) {
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int r = t + TB * i;
+      smem[r * kC + (col ^ ((r >> 3) & 3))] = v[i];
+    }
+  }
+  __syncthreads();
+  cf *const dst = out + clip * out_clip + size_t(jt) * LB * kC;
+#pragma unroll 4
+  for (int e = threadIdx.x; e < LB * kC; e += RS::threads) {
+    const int r = e >> 2;
+    dst[e] = cscale(smem[(e & ~3) + ((e & 3) ^ ((r >> 3) & 3))], scale);
+  }
+}
+
 // Twiddles of the k-loop passes are staged in LDS when the table is small
 // next to the exchange buffers: table reads then wait on the LDS counter only,
 // not behind the prefetched band loads in flight on the vector-memory counter
@@ -1721,6 +1817,17 @@ int col_fft_l(const char *name, const cf *in, cf *out, int nt, int in_h, int out
   });
 }
 
+template <int LA, int DIRA, int LB, int DIRB>
+int col_resample_l(const char *name, const cf *in, cf *out, int nt, int h, const cf *twA, const cf *twB,
+                   float scale, float gc, int nclips, hipStream_t s) {
+  using RS = dev::Resample<LA, LB>;
+  const dim3 grid(nt, nclips);
+  return launch(name, KPTR(dev::k_col_resample<LA, DIRA, LB, DIRB>), grid, RS::bytes, s, [&] {
+    hipLaunchKernelGGL((dev::k_col_resample<LA, DIRA, LB, DIRB>), grid, dim3(RS::threads), RS::bytes, s, in, out, h,
+                       size_t(nt) * LA * kC, size_t(nt) * LB * kC, twA, twB, scale, gc);
+  });
+}
+
 template <int Q>
 int pass_y_fwd_q(const cf *bank, const cf *Mh, cf *Y, const PassGeo &pg, const cf *twQ, int nclips,
                  hipStream_t s) {
@@ -2040,6 +2147,28 @@ int run_col_fft(const char *name, int L, int dir, const cf2 *in, cf2 *out, int n
   }
   LITHO_DISPATCH_Q(L, (col_fft_l<NN, +1>(name, (const cf *)in, (cf *)out, nt, in_h, out_h, (const cf *)tw, scale,
                                           nclips, s)));
+}
+// The resampling pairs with a fused column pass: the inner grids of the
+// 1024^2 and 2048^2 clips.  Other pairs take the two column transforms.
+bool col_resample_ok(int Q, int N) { return (Q == 640 && N == 1024) || (Q == 1280 && N == 2048); }
+int run_col_resample(const char *name, int Q, int N, bool up, const cf2 *in, cf2 *out, int nt, int h,
+                     const cf2 *twQ, const cf2 *twN, float scale, double blur_sigma_px, int nclips, hipStream_t s) {
+  const float gc = blur_sigma_px > 0.0
+                       ? float(2.0 * 3.14159265358979323846 * 3.14159265358979323846 * blur_sigma_px * blur_sigma_px /
+                               (double(N) * double(N)))
+                       : 0.f;
+  const cf *i = (const cf *)in, *tq = (const cf *)twQ, *tn = (const cf *)twN;
+  cf *o = (cf *)out;
+  if (Q == 640 && N == 1024) {
+    if (up) return col_resample_l<640, -1, 1024, +1>(name, i, o, nt, h, tq, tn, scale, gc, nclips, s);
+    return col_resample_l<1024, -1, 640, +1>(name, i, o, nt, h, tn, tq, scale, gc, nclips, s);
+  }
+  if (Q == 1280 && N == 2048) {
+    if (up) return col_resample_l<1280, -1, 2048, +1>(name, i, o, nt, h, tq, tn, scale, gc, nclips, s);
+    return col_resample_l<2048, -1, 1280, +1>(name, i, o, nt, h, tn, tq, scale, gc, nclips, s);
+  }
+  set_error("%s: no fused resampling pass between %d and %d", name, Q, N);
+  return LITHO_E_UNSUPPORTED;
 }
 int run_pass_y_fwd(const cf2 *bank, const cf2 *Mh, cf2 *Y, const PassGeo &pg, const cf2 *twQ, int nclips,
                    hipStream_t s) {

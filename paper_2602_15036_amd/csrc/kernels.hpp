@@ -62,6 +62,13 @@ int run_rows_inv_thresh(const char *name, int L, const cf2 *in, int h, int Wp, f
                         const cf2 *tw, float scale, int nclips, hipStream_t s);
 int run_col_fft(const char *name, int L, int dir, const cf2 *in, cf2 *out, int nt, int in_h, int out_h,
                 const cf2 *tw, float scale, int nclips, hipStream_t s);
+// Both column transforms of a band resampling between the inner grid Q and
+// the clip grid N in one pass (up: Q rows -> band |f| <= h -> N rows; down:
+// N rows -> band -> Q rows), with the resist Gaussian on the band when
+// blur_sigma_px > 0.  Only for the pairs col_resample_ok accepts.
+bool col_resample_ok(int Q, int N);
+int run_col_resample(const char *name, int Q, int N, bool up, const cf2 *in, cf2 *out, int nt, int h,
+                     const cf2 *twQ, const cf2 *twN, float scale, double blur_sigma_px, int nclips, hipStream_t s);
 int run_pass_y_fwd(const cf2 *bank, const cf2 *Mh, cf2 *Y, const PassGeo &g, const cf2 *twQ, int nclips,
                    hipStream_t s);
 int run_pass_x_fwd(const cf2 *Y, const EpiPtrs &ep, cf2 *Ib, const PassGeo &g, const cf2 *twQ, int nclips,
