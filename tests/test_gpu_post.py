@@ -9,6 +9,9 @@
 * litho_image_grad with a Gaussian resist kernel (Eq. 5) and the L2 or L1
   loss (Eqs. 15-17): resist image 1e-5, loss 1e-5, gradient 1e-4 (relative).
 * litho_ai_channels (Eq. 9): layout exact, image and dI/dM within 1e-5.
+* The fused resampling column pass (with the resist blur folded in) against
+  the two-pass route of another inner grid at 1024^2 and 2048^2: the blurred
+  ILT step's image and loss within 2e-6, its gradient within 1e-5.
 
 Every input is seeded and synthetic (workloads) or computed by the oracle,
 rounded to float32 and given to both sides.
@@ -265,6 +268,33 @@ def test_litho_consistency_loss(L):
     Lo, go, _ = OP.blurred_gradient(m, Zr, _banks(spec, 8), SLOPE, tau_print, 0.0, loss="l1")
     assert abs(lo.item() - Lo) < 1e-5 * Lo
     assert rel_l2(grad.cpu().numpy()[0], go) < 1e-4
+
+
+@pytest.mark.parametrize("spec_name,fused_q,plain_q,nb", [("CONFIG2", 640, 768, 2), ("CONFIG3", 1280, 1536, 1)])
+def test_fused_resampling_pass_against_the_two_pass_route(L, spec_name, fused_q, plain_q, nb):
+    """The inner grids 640 (of 1024) and 1280 (of 2048) resample through one
+    column pass per direction with the resist Gaussian folded in; 768 and
+    1536 take two column passes and a band multiply.  Both resamplings are
+    exact, so the blurred ILT step agrees across the two routes to FP32
+    rounding, at full size."""
+    spec = getattr(W, spec_name)
+    if spec_name == "CONFIG3":
+        spec = spec.with_(focus_nm=(0.0,))
+    n = spec.n
+    bank = L.Bank.from_spec(spec)
+    m = np.stack([W.as_f32_exact(W.curvilinear_mask(n, 60 + i)) for i in range(nb)])
+    T = np.stack([W.manhattan_target(n, 70 + i) for i in range(nb)]).astype(np.float32)
+    out = {}
+    for q in (fused_q, plain_q):
+        bank.set_inner_grid(q)
+        assert bank.inner_grid == q
+        img, lo, g = L.image_grad(bank, dev(m), target=dev(T), slope=SLOPE, threshold=THR, blur_sigma_px=2.5)
+        out[q] = (img.cpu().numpy(), lo.cpu().numpy().astype(np.float64), g.cpu().numpy())
+    (i0, l0, g0), (i1, l1, g1) = out[fused_q], out[plain_q]
+    e_img, e_loss, e_grad = rel_l2(i0, i1), float(np.max(np.abs(l0 - l1) / np.abs(l1))), rel_l2(g0, g1)
+    print(f"resampling routes n={n} Q={fused_q} vs {plain_q}: resist image {e_img:.2e} loss {e_loss:.2e} "
+          f"grad {e_grad:.2e}")
+    assert e_img < 2e-6 and e_loss < 2e-6 and e_grad < 1e-5
 
 
 # ---------------------------------------------------------------- Eq. 9 channels
