@@ -658,8 +658,9 @@ template <int LA, int LB>
 struct Resample {
   static constexpr int TA = FftPlan<LA>::T, TB = FftPlan<LB>::T;
   static constexpr int threads = 4 * (TA > TB ? TA : TB);
+  // half-width exchanges: the band staging then sets the workgroup's LDS
   static constexpr bool HA = HalfPlan<LA>::ok, HB = HalfPlan<LB>::ok;
-  // band rows of one column in LDS (at most min(LA, LB)), plus a pad slot
+  // band rows of one column in LDS (at most min(LA, LB)), plus two pad slots
   static constexpr int stage = (LA < LB ? LA : LB) + 2;
   static constexpr size_t bytes_a = size_t(4) * Xch<LA, HA>::floats * sizeof(float);
   static constexpr size_t bytes_b = size_t(4) * Xch<LB, HB>::floats * sizeof(float);
@@ -667,9 +668,11 @@ struct Resample {
   static constexpr size_t bytes_o = size_t(LB) * kC * sizeof(cf);
   static constexpr size_t m1 = bytes_a > bytes_b ? bytes_a : bytes_b, m2 = bytes_s > bytes_o ? bytes_s : bytes_o;
   static constexpr size_t bytes = m1 > m2 ? m1 : m2;
-  // each transform's threads fill whole wavefronts (its exchanges synchronise
-  // one wavefront)
+  // each transform's threads fill whole wavefronts, and its exchanges
+  // synchronise only its own wavefront (transforms wider than a wavefront
+  // would need the workgroup barrier inside the per-column branches)
   static_assert((4 * TA) % 64 == 0 && (4 * TB) % 64 == 0, "transforms must fill whole wavefronts");
+  static_assert(TA <= 64 && TB <= 64, "one wavefront per transform at most");
 };
 template <int LA, int DIRA, int LB, int DIRB>
 __global__ __launch_bounds__((Resample<LA, LB>::threads)) void k_col_resample(const cf *__restrict__ in,
