@@ -4,7 +4,7 @@ both ways, band multiply, inverse row DFT to real rows), against the oracle's
 FP64 periodic Gaussian filter.  Together with the imaging tests (which run the
 per-kernel passes on each inner grid they reach) this exercises every FFT
 plan and its LDS exchange schedule on the GPU.  Gate: 1e-6 of the image's
-largest value (FP32 transforms of length <= 4096; measured 1.4e-7 to 5.8e-7).
+largest value (FP32 transforms of length <= 4096; measured 1.4e-7 to 5.6e-7).
 """
 import numpy as np
 import pytest
